@@ -1,0 +1,183 @@
+"""Pins of the image-stage oracle against facts fixed outside it: published hash
+vectors, hand-derived golden cases, closed forms, invariants and library routines."""
+import os
+
+import numpy as np
+import pytest
+import scipy.ndimage
+
+import synth
+
+GOLD = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _rand(seed, H, W):
+    return synth.image(seed, H, W)
+
+
+# ------------------------------------------------------------------ noise
+def test_fmix32_published_vectors(orc):
+    # MurmurHash3_x86_32 with an empty key reduces to fmix32(seed); values are the
+    # published test vectors (see tests/golden/noise_hash_vectors.txt).
+    assert orc.fmix32(0) == 0
+    assert orc.fmix32(1) == 0x514E28B7
+    assert orc.fmix32(0xFFFFFFFF) == 0x81F16F39
+    assert orc.fmix32(0xE6546B60) == 0x2362F9DE
+
+
+def _noise_cases():
+    rows = []
+    with open(os.path.join(GOLD, "noise_hash_vectors.txt")) as f:
+        for line in f:
+            line = line.strip()
+            if not line or line.startswith("#"):
+                continue
+            t = line.split()
+            rows.append((int(t[0], 16), int(t[1]), int(t[2]),
+                         [int(v) for v in t[3:7]], [int(v) for v in t[7:11]]))
+    return rows
+
+
+@pytest.mark.parametrize("case", _noise_cases())
+def test_noise_golden(orc, case):
+    seed, x, y, pin, pout = case
+    W, H = 9, 6
+    img = _rand(11, H, W)
+    img[y, x] = pin
+    out = orc.noise(img, seed)
+    assert list(out[y, x]) == pout
+
+
+def test_noise_offsets_range_and_coverage(orc):
+    img = np.full((64, 96, 4), 128, np.uint8)
+    out = orc.noise(img, 0x1510).astype(int) - 128
+    assert out.min() == -16 and out.max() == 16
+    assert len(np.unique(out)) == 33
+    # roughly uniform over the 33 offsets (256 = 7*33 + 25 byte values)
+    counts = np.bincount((out + 16).ravel(), minlength=33)
+    assert counts.min() > 0.5 * counts.mean()
+
+
+def test_noise_clamps(orc):
+    lo = np.zeros((8, 8, 4), np.uint8)
+    hi = np.full((8, 8, 4), 255, np.uint8)
+    assert orc.noise(lo, 5).max() <= 16
+    assert orc.noise(hi, 5).min() >= 239
+    # noise depends on the pixel coordinate: a different seed gives a different field
+    a, b = orc.noise(np.full((8, 8, 4), 100, np.uint8), 1), orc.noise(np.full((8, 8, 4), 100, np.uint8), 2)
+    assert (a != b).any()
+
+
+def test_noise_rejects_oversized(orc):
+    with pytest.raises(ValueError):
+        orc.noise(np.zeros((1, 65537, 4), np.uint8), 0)
+
+
+# ----------------------------------------------------------------- solarise
+def test_solarise_exhaustive(orc):
+    v = np.arange(256, dtype=np.uint8).reshape(1, 64, 4)
+    s = orc.solarise(v).ravel().astype(int)
+    ref = np.minimum(np.arange(256), 255 - np.arange(256))   # equivalent closed form
+    assert (s == ref).all()
+    assert s.max() == 127
+    assert (orc.solarise(orc.solarise(v)) == orc.solarise(v)).all()     # idempotent
+    fixed = np.arange(128)
+    assert (s[fixed] == fixed).all()                                      # fixed points v <= 127
+
+
+# ------------------------------------------------------------------- mirror
+@pytest.mark.parametrize("H,W", [(1, 1), (3, 5), (17, 33), (8, 1)])
+def test_mirror_is_row_reversal(orc, H, W):
+    img = _rand(H * 100 + W, H, W)
+    m = orc.mirror(img)
+    assert (m == img[:, ::-1, :]).all()         # library reversal of whole pixels
+    assert (orc.mirror(m) == img).all()          # involution
+
+
+def test_mirror_commutes_with_pointwise_and_blur_not_noise(orc):
+    img = _rand(3, 9, 7)
+    assert (orc.mirror(orc.solarise(img)) == orc.solarise(orc.mirror(img))).all()
+    assert (orc.mirror(orc.blur5(img)) == orc.blur5(orc.mirror(img))).all()
+    assert (orc.mirror(orc.noise(img, 9)) != orc.noise(orc.mirror(img), 9)).any()
+
+
+# --------------------------------------------------------------------- blur
+def _blur_cases():
+    cases, cur = [], None
+    with open(os.path.join(GOLD, "blur5_impulse.txt")) as f:
+        for line in f:
+            line = line.strip()
+            if not line or line.startswith("#"):
+                continue
+            t = line.split()
+            if t[0] == "case":
+                cur = {"W": int(t[1]), "H": int(t[2]), "px": int(t[3]), "py": int(t[4]),
+                       "V": int(t[5]), "rows": []}
+                cases.append(cur)
+            else:
+                cur["rows"].append([int(v) for v in t])
+    return cases
+
+
+@pytest.mark.parametrize("case", _blur_cases(), ids=lambda c: "W%dH%d_%d_%d_V%d" % (c["W"], c["H"], c["px"], c["py"], c["V"]))
+def test_blur_golden_impulses(orc, case):
+    img = np.zeros((case["H"], case["W"], 4), np.uint8)
+    img[case["py"], case["px"], 0] = case["V"]
+    out = orc.blur5(img)
+    assert out[:, :, 0].tolist() == case["rows"]
+    assert (out[:, :, 1:] == 0).all()
+
+
+@pytest.mark.parametrize("H,W", [(1, 1), (2, 3), (13, 17), (31, 9), (64, 70)])
+def test_blur_matches_library_correlate(orc, H, W):
+    img = _rand(H * 7 + W, H, W)
+    out = orc.blur5(img)
+    # scipy's correlate with mode='nearest' is clamp-to-edge; exact integer sums
+    ref = scipy.ndimage.correlate(img.astype(np.int64), np.ones((5, 5, 1), np.int64), mode="nearest") // 25
+    assert (out == ref.astype(np.uint8)).all()
+
+
+def test_blur_constant_and_bounds(orc):
+    for v in (0, 1, 77, 127, 255):
+        img = np.full((11, 6, 4), v, np.uint8)
+        assert (orc.blur5(img) == v).all()
+    img = orc.solarise(_rand(5, 20, 20))
+    assert orc.blur5(img).max() <= 127
+
+
+# ------------------------------------------------------------ hist and sum
+@pytest.mark.parametrize("H,W", [(1, 1), (5, 7), (64, 33)])
+def test_hist_sum_library(orc, H, W):
+    img = _rand(H + W, H, W)
+    hist, s = orc.hist_sum(img)
+    for c in range(4):
+        assert (hist[c] == np.bincount(img[:, :, c].ravel(), minlength=256)).all()
+        assert int(s[c]) == int(img[:, :, c].astype(np.int64).sum())
+        assert int(hist[c].sum()) == H * W
+        assert int(s[c]) == int((np.arange(256) * hist[c].astype(np.int64)).sum())
+    h2, s2 = orc.hist_sum(orc.mirror(img))
+    assert (h2 == hist).all() and (s2 == s).all()
+
+
+def test_hist_after_solarise_upper_bins_empty(orc):
+    hist, _ = orc.hist_sum(orc.solarise(_rand(8, 40, 40)))
+    assert (hist[:, 128:] == 0).all()
+
+
+# ---------------------------------------------------------------- pipelines
+def test_pipeline_order_is_stage_order(orc):
+    img = _rand(1, 16, 12)
+    st = [("noise", {"seed": 0x1510}), ("solarise", {}), ("blur5", {}), ("mirror", {})]
+    out, hist, s = orc.run_image_pipeline(img, st, "hist_sum")
+    manual = orc.mirror(orc.blur5(orc.solarise(orc.noise(img, 0x1510))))
+    assert (out == manual).all()
+    h2, s2 = orc.hist_sum(manual)
+    assert (hist == h2).all() and (s == s2).all()
+    # reordering noise and mirror changes the result: noise is position dependent
+    swapped = orc.run_image_pipeline(img, [("mirror", {}), ("noise", {"seed": 0x1510})])
+    assert (swapped != orc.run_image_pipeline(img, [("noise", {"seed": 0x1510}), ("mirror", {})])).any()
+
+
+def test_image_rows_generator_matches_full_draw():
+    a = synth.image(7, 37, 53)
+    assert (synth.image_rows(7, 37, 53, 5, 20) == a[5:20]).all()
