@@ -14,6 +14,8 @@
  *
  * Images are RGBA uint8, row-major, dense: byte (y*W + x)*4 + c.
  * Build: gcc -O2 -fopenmp -ffp-contract=off -shared -fPIC (no -ffast-math).
+ * OpenMP only splits loops over independent output rows or bodies, so every
+ * result is independent of the thread count.
  */
 #include <math.h>
 #include <stdint.h>
@@ -49,6 +51,7 @@ int orc_noise_offset(uint32_t seed, int64_t x, int64_t y, int c) {
 
 int orc_noise(const uint8_t* in, uint8_t* out, int64_t W, int64_t H, uint32_t seed) {
     if (W < 0 || H < 0 || W > 65536 || H > 65536) return -1;
+#pragma omp parallel for schedule(static)
     for (int64_t y = 0; y < H; ++y)
         for (int64_t x = 0; x < W; ++x)
             for (int c = 0; c < 4; ++c) {
@@ -88,6 +91,7 @@ void orc_mirror(const uint8_t* in, uint8_t* out, int64_t W, int64_t H) {
 static int64_t clampi(int64_t v, int64_t lo, int64_t hi) { return v < lo ? lo : (v > hi ? hi : v); }
 
 void orc_blur5(const uint8_t* in, uint8_t* out, int64_t W, int64_t H) {
+#pragma omp parallel for schedule(static)
     for (int64_t y = 0; y < H; ++y)
         for (int64_t x = 0; x < W; ++x)
             for (int c = 0; c < 4; ++c) {

@@ -1,0 +1,455 @@
+// C-ABI entry points: SCT construction, plan compilation and execution
+// requests (Table 1 of the paper), the device-resident Loop driver and the
+// batched executor.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdio>
+#include <cstring>
+#include <new>
+
+#include "internal.h"
+
+using namespace skel;
+
+#define HIP_TRY(expr)                                                                          \
+    do {                                                                                       \
+        hipError_t e_ = (expr);                                                                \
+        if (e_ != hipSuccess)                                                                  \
+            return set_error(e_ == hipErrorOutOfMemory ? SKEL_ENOMEM : SKEL_EDEVICE, "%s: %s", \
+                             #expr, hipGetErrorString(e_));                                    \
+    } while (0)
+
+namespace {
+
+void node_addref(skel_node_s* n) {
+    if (n) n->refs.fetch_add(1);
+}
+
+void node_release(skel_node_s* n) {
+    if (!n) return;
+    if (n->refs.fetch_sub(1) == 1) {
+        for (skel_node_s* k : n->kids) node_release(k);
+        delete n;
+    }
+}
+
+skel_status new_node(skel_node* out, skel_node_s** n) {
+    if (!out) return set_error(SKEL_EINVAL, "null output handle");
+    *out = nullptr;
+    *n = new (std::nothrow) skel_node_s();
+    if (!*n) return set_error(SKEL_ENOMEM, "host allocation failed");
+    return SKEL_OK;
+}
+
+inline hipStream_t S(void* s) { return (hipStream_t)s; }
+
+// Byte range of a buffer, for overlap checks.
+struct Range {
+    uintptr_t lo, hi;
+};
+Range range_of(const skel_buffer& b) {
+    int64_t bytes = b.ndim > 0 ? 1 : 0;
+    for (int d = 0; d < b.ndim; ++d) bytes *= b.shape[d];
+    const int64_t es = (b.dtype == SKEL_U8) ? 1 : ((b.dtype == SKEL_U64 || b.dtype == SKEL_F64) ? 8 : 4);
+    return Range{(uintptr_t)b.data, (uintptr_t)b.data + (uintptr_t)(bytes * es)};
+}
+bool overlap(const skel_buffer& a, const skel_buffer& b) {
+    const Range x = range_of(a), y = range_of(b);
+    return x.lo < y.hi && y.lo < x.hi && x.hi > x.lo && y.hi > y.lo;
+}
+
+skel_status check_args(skel_plan p, const skel_buffer* args, int32_t nargs) {
+    if (!p) return set_error(SKEL_EINVAL, "null plan");
+    if (nargs != (int32_t)p->proto.size())
+        return set_error(SKEL_EINVAL, "plan takes %d arguments, got %d", (int)p->proto.size(), nargs);
+    if (nargs && !args) return set_error(SKEL_EINVAL, "null argument array");
+    for (int k = 0; k < nargs; ++k) {
+        const skel_buffer& a = args[k];
+        const skel_buffer& q = p->proto[k];
+        if (a.dtype != q.dtype) return set_error(SKEL_ETYPE, "argument %d: dtype differs from the compiled plan", k);
+        if (a.ndim != q.ndim) return set_error(SKEL_ESHAPE, "argument %d: rank differs from the compiled plan", k);
+        for (int d = 0; d < a.ndim; ++d)
+            if (a.shape[d] != q.shape[d])
+                return set_error(SKEL_ESHAPE, "argument %d: shape differs from the compiled plan (recompile for new shapes)", k);
+        int64_t es = (a.dtype == SKEL_U8) ? 1 : ((a.dtype == SKEL_U64 || a.dtype == SKEL_F64) ? 8 : 4), st = es;
+        for (int d = a.ndim - 1; d >= 0; --d) {
+            if (a.stride_bytes[d] != 0 && a.stride_bytes[d] != st && a.shape[d] > 1)
+                return set_error(SKEL_ESHAPE, "argument %d: not dense row-major", k);
+            st *= a.shape[d];
+        }
+        if (!a.data && range_of(a).hi != range_of(a).lo) return set_error(SKEL_EINVAL, "argument %d: null data", k);
+    }
+    return SKEL_OK;
+}
+
+skel_status check_aliasing(skel_plan p, const skel_buffer* args) {
+    const Linear& L = p->lin;
+    if (L.dom == DOM_U8) {
+        const bool same = args[0].data == args[1].data && range_of(args[0]).hi > range_of(args[0]).lo;
+        if (overlap(args[0], args[1]) && !same) return set_error(SKEL_EINVAL, "input and output overlap partially");
+        if (same) {
+            for (const Kernel& k : p->kernels)
+                if (k.src == -1 && k.dst == -2 && (k.blur || k.img.in_flip || k.img.out_flip))
+                    return set_error(SKEL_EINVAL, "in-place run of a kernel with a stencil or a mirror");
+        }
+        for (int k = 2; k < (int)p->proto.size(); ++k)
+            for (int j = 0; j < 2; ++j)
+                if (overlap(args[k], args[j])) return set_error(SKEL_EINVAL, "reduce output overlaps an image");
+        if (p->proto.size() == 4 && overlap(args[2], args[3])) return set_error(SKEL_EINVAL, "hist and sum overlap");
+    } else if (L.dom == DOM_F32) {
+        const int out = 1 + (int)std::count_if(L.st.begin(), L.st.end(), [](const Stage& s) { return s.op == SKEL_OP_SAXPY; });
+        for (int k = 0; k < (int)p->proto.size(); ++k) {
+            if (k == out) continue;
+            if (!overlap(args[k], args[out])) continue;
+            if (k == 0 && args[0].data == args[out].data) {
+                for (const Kernel& kk : p->kernels)
+                    if (kk.src == -1 && kk.dst == -2 && (kk.vec.out_flip || kk.vec.in_flip))
+                        return set_error(SKEL_EINVAL, "in-place run of a kernel with a reversal");
+                continue;
+            }
+            return set_error(SKEL_EINVAL, "argument %d overlaps the output", k);
+        }
+    } else if (L.dom == DOM_NBODY) {
+        for (int a = 0; a < 3; ++a)
+            for (int b = a + 1; b < 3; ++b)
+                if (overlap(args[a], args[b])) return set_error(SKEL_EINVAL, "N-body buffers must not overlap");
+    }
+    return SKEL_OK;
+}
+
+void* resolve_img(skel_plan p, const skel_buffer* args, int id) {
+    if (id == -1) return args[0].data;
+    if (id == -2) return args[1].data;
+    if (id == 0 || id == 1) return p->scratch[id];
+    return nullptr;
+}
+
+skel_status run_image(skel_plan p, const skel_buffer* args, hipStream_t s) {
+    const Linear& L = p->lin;
+    if (L.red == SKEL_RED_HIST256_SUM) {
+        HIP_TRY(launch_fill_u32(args[2].data, 1024, 0, s));
+        HIP_TRY(launch_fill_u32(args[3].data, 8, 0, s));
+    } else if (L.red == SKEL_RED_SUM) {
+        HIP_TRY(launch_fill_u32(args[2].data, 8, 0, s));
+    }
+    for (Kernel& k : p->kernels) {
+        ImgGroupArgs A = k.img;
+        A.in = (const uint8_t*)resolve_img(p, args, k.src);
+        A.out = (uint8_t*)resolve_img(p, args, k.dst);
+        if (k.reduce) {
+            A.hist = L.red == SKEL_RED_HIST256_SUM ? (uint32_t*)args[2].data : nullptr;
+            A.sum = L.red == SKEL_RED_HIST256_SUM ? (uint64_t*)args[3].data : (uint64_t*)args[2].data;
+        }
+        HIP_TRY(launch_img_group(A, k.blur, k.reduce, k.wg, p->cfg.variant, s, &k.name));
+    }
+    return SKEL_OK;
+}
+
+skel_status run_vector(skel_plan p, const skel_buffer* args, hipStream_t s) {
+    const Linear& L = p->lin;
+    const int nargs = (int)p->proto.size();
+    const int out = nargs - 1 - (L.red >= 0 ? 1 : 0);
+    float* sum_out = L.red >= 0 ? (float*)args[nargs - 1].data : nullptr;
+    if (L.red >= 0 && p->sh.n == 0) HIP_TRY(launch_fill_u32(sum_out, 1, 0, s));
+    for (Kernel& k : p->kernels) {
+        VecGroupArgs A = k.vec;
+        auto res = [&](int id) -> float* {
+            if (id == -1) return (float*)args[0].data;
+            if (id == -2) return (float*)args[out].data;
+            if (id == 0 || id == 1) return (float*)p->scratch[id];
+            return nullptr;
+        };
+        A.in = res(k.src);
+        A.out = res(k.dst);
+        for (size_t j = 0; j < k.side_args.size(); ++j) A.side[j] = (const float*)args[k.side_args[j]].data;
+        if (k.reduce && p->sh.n > 0) {
+            A.partials = p->partials;
+            A.ticket = p->ticket;
+            A.sum_out = sum_out;
+        }
+        HIP_TRY(launch_vec_group(A, k.grid, k.wg, s, &k.name));
+    }
+    return SKEL_OK;
+}
+
+skel_status nbody_iterations(skel_plan p, float4* pos, float4* vel, float4* scr, hipStream_t s) {
+    const Linear& L = p->lin;
+    NBodyArgs A{};
+    A.vel = vel;
+    A.acc = p->nb_acc;
+    A.N = (int32_t)p->sh.N;
+    A.jsplit = p->cfg.tile_h;
+    A.eps2 = L.nbody_prm.eps * L.nbody_prm.eps;
+    A.G = L.nbody_prm.G;
+    A.dt = L.nbody_prm.dt;
+    const bool fused = p->cfg.fusion != SKEL_FUSE_OFF;
+    for (int t = 0; t < L.nbody_iters; ++t) {
+        A.pos_in = (t % 2 == 0) ? pos : scr;
+        A.pos_out = (t % 2 == 0) ? scr : pos;
+        HIP_TRY(launch_nbody_force(A, fused, s, &p->kernels[0].name));
+        if (!fused) HIP_TRY(launch_nbody_integrate(A, s, &p->kernels[1].name));
+    }
+    if (L.nbody_iters % 2 == 1) HIP_TRY(launch_copy_f32x4(scr, pos, p->sh.N, s));
+    return SKEL_OK;
+}
+
+// Loop driver: the whole counted loop is captured once into a HIP graph (per
+// set of buffers) and replayed, so the loop state never leaves the device and
+// no host round trip separates iterations (the paper runs the condition and
+// state update on the host, Sec. 3.1).
+skel_status run_nbody(skel_plan p, const skel_buffer* args, hipStream_t s) {
+    float4* pos = (float4*)args[0].data;
+    float4* vel = (float4*)args[1].data;
+    float4* scr = (float4*)args[2].data;
+    if (p->sh.N == 0 || p->lin.nbody_iters == 0) return SKEL_OK;
+    if (p->cfg.variant == 1) return nbody_iterations(p, pos, vel, scr, s);
+    std::vector<const void*> key = {pos, vel, scr};
+    if (!p->gexec || key != p->gkey) {
+        if (p->gexec) {
+            HIP_TRY(hipGraphExecDestroy(p->gexec));
+            p->gexec = nullptr;
+        }
+        if (!p->cap_stream) HIP_TRY(hipStreamCreateWithFlags(&p->cap_stream, hipStreamNonBlocking));
+        HIP_TRY(hipStreamBeginCapture(p->cap_stream, hipStreamCaptureModeThreadLocal));
+        skel_status st = nbody_iterations(p, pos, vel, scr, p->cap_stream);
+        hipGraph_t g = nullptr;
+        hipError_t e = hipStreamEndCapture(p->cap_stream, &g);
+        if (st) {
+            if (g) hipGraphDestroy(g);
+            return st;
+        }
+        if (e != hipSuccess) return set_error(SKEL_EDEVICE, "graph capture failed: %s", hipGetErrorString(e));
+        e = hipGraphInstantiate(&p->gexec, g, nullptr, nullptr, 0);
+        hipGraphDestroy(g);
+        if (e != hipSuccess) return set_error(SKEL_EDEVICE, "graph instantiate failed: %s", hipGetErrorString(e));
+        p->gkey = key;
+    }
+    HIP_TRY(hipGraphLaunch(p->gexec, s));
+    return SKEL_OK;
+}
+
+// Device resources of a plan are allocated on its first run, so compiling a
+// plan is a host-only step: intermediate images/vectors between unfused
+// kernels, reduce partials and the unfused N-body acceleration buffer.
+skel_status ensure_resources(skel_plan p) {
+    if (p->resources_ready) return SKEL_OK;
+    int nscr = 0;
+    for (const Kernel& k : p->kernels) nscr = std::max(nscr, k.dst >= 0 ? k.dst + 1 : 0);
+    size_t bytes = 0;
+    if (p->lin.dom == DOM_U8) bytes = (size_t)(p->sh.W * p->sh.H * 4);
+    if (p->lin.dom == DOM_F32) bytes = (size_t)(p->sh.n * 4);
+    for (int k = 0; k < nscr; ++k)
+        if (!p->scratch[k]) HIP_TRY(hipMalloc(&p->scratch[k], std::max<size_t>(bytes, 16)));
+    if (p->lin.dom == DOM_F32 && p->lin.red >= 0 && !p->partials) {
+        int g = 1;
+        for (const Kernel& k : p->kernels)
+            if (k.reduce) g = std::max(g, k.grid);
+        HIP_TRY(hipMalloc(&p->partials, sizeof(float) * g));
+        HIP_TRY(hipMalloc(&p->ticket, 256));
+        HIP_TRY(hipMemset(p->ticket, 0, 256));
+    }
+    if (p->lin.dom == DOM_NBODY && p->cfg.fusion == SKEL_FUSE_OFF && !p->nb_acc)
+        HIP_TRY(hipMalloc(&p->nb_acc, sizeof(float4) * std::max<int64_t>(p->sh.N, 1)));
+    p->resources_ready = true;
+    return SKEL_OK;
+}
+
+}  // namespace
+
+skel_status skel_ensure_resources(skel_plan p) { return ensure_resources(p); }
+
+extern "C" {
+
+skel_status skel_init(int32_t device) {
+    clear_error();
+    int n = 0;
+    HIP_TRY(hipGetDeviceCount(&n));
+    if (device < 0 || device >= n) return set_error(SKEL_EINVAL, "device %d of %d", device, n);
+    HIP_TRY(hipSetDevice(device));
+    hipDeviceProp_t prop;
+    HIP_TRY(hipGetDeviceProperties(&prop, device));
+    if (strncmp(prop.gcnArchName, "gfx950", 6) != 0)
+        return set_error(SKEL_EUNSUPPORTED, "device %d is %s; this library is built for gfx950", device, prop.gcnArchName);
+    return SKEL_OK;
+}
+
+skel_status skel_map(int32_t op, const skel_params* p, skel_node* out) {
+    clear_error();
+    if (op < SKEL_OP_NOISE || op > SKEL_OP_LEAPFROG) return set_error(SKEL_EINVAL, "unknown stage op %d", op);
+    skel_node_s* n;
+    skel_status st = new_node(out, &n);
+    if (st) return st;
+    n->kind = NK_MAP;
+    n->op = op;
+    if (p) n->prm = *p;
+    *out = n;
+    return SKEL_OK;
+}
+
+skel_status skel_pipeline(const skel_node* stages, int32_t count, skel_node* out) {
+    clear_error();
+    if (count < 1 || !stages) return set_error(SKEL_EINVAL, "a pipeline needs at least one stage");
+    for (int k = 0; k < count; ++k)
+        if (!stages[k]) return set_error(SKEL_EINVAL, "pipeline stage %d is null", k);
+    skel_node_s* n;
+    skel_status st = new_node(out, &n);
+    if (st) return st;
+    n->kind = NK_PIPE;
+    for (int k = 0; k < count; ++k) {
+        node_addref(stages[k]);
+        n->kids.push_back(stages[k]);
+    }
+    *out = n;
+    return SKEL_OK;
+}
+
+skel_status skel_mapreduce(skel_node map, int32_t red, skel_node* out) {
+    clear_error();
+    if (!map) return set_error(SKEL_EINVAL, "null map node");
+    if (red != SKEL_RED_HIST256_SUM && red != SKEL_RED_SUM) return set_error(SKEL_EINVAL, "unknown reduce %d", red);
+    if (map->kind == NK_MAPRED) return set_error(SKEL_EINVAL, "nested MapReduce");
+    skel_node_s* n;
+    skel_status st = new_node(out, &n);
+    if (st) return st;
+    n->kind = NK_MAPRED;
+    n->red = red;
+    node_addref(map);
+    n->kids.push_back(map);
+    *out = n;
+    return SKEL_OK;
+}
+
+skel_status skel_loop(skel_node body, const skel_loop_state* ls, skel_node* out) {
+    clear_error();
+    if (!body || !ls) return set_error(SKEL_EINVAL, "null loop body or state");
+    if (ls->iterations < 0) return set_error(SKEL_EINVAL, "negative iteration count");
+    if (body->kind == NK_MAPRED) return set_error(SKEL_EINVAL, "MapReduce is only valid at the root of a plan");
+    skel_node_s* n;
+    skel_status st = new_node(out, &n);
+    if (st) return st;
+    n->kind = NK_LOOP;
+    n->loop = *ls;
+    node_addref(body);
+    n->kids.push_back(body);
+    *out = n;
+    return SKEL_OK;
+}
+
+skel_status skel_node_release(skel_node node) {
+    clear_error();
+    node_release(node);
+    return SKEL_OK;
+}
+
+skel_status skel_plan_compile(skel_node root, const skel_buffer* proto, int32_t nargs, const skel_plan_opts* opts,
+                              skel_plan* out) {
+    clear_error();
+    if (!out) return set_error(SKEL_EINVAL, "null output handle");
+    *out = nullptr;
+    if (!root) return set_error(SKEL_EINVAL, "null root node");
+    if (nargs < 0 || (nargs > 0 && !proto)) return set_error(SKEL_EINVAL, "bad prototype arguments");
+    skel_plan_s* p = new (std::nothrow) skel_plan_s();
+    if (!p) return set_error(SKEL_ENOMEM, "host allocation failed");
+    skel_status st = linearize(root, p->lin);
+    if (!st && p->lin.dom == DOM_NONE) {
+        p->lin.dom = (nargs > 0 && proto[0].dtype == SKEL_U8) ? DOM_U8 : DOM_F32;
+        if (p->lin.dom == DOM_F32 && p->lin.red == SKEL_RED_HIST256_SUM)
+            st = set_error(SKEL_ETYPE, "the histogram reduce applies to RGBA uint8 images only");
+    }
+    if (!st) st = derive_shape(p->lin, proto, nargs, p->sh);
+    if (!st) st = resolve_config(p->lin, p->sh, opts, p->cfg);
+    if (!st) st = build_kernels(p->lin, p->sh, p->cfg, p->kernels);
+    if (st) {
+        delete p;
+        return st;
+    }
+    p->proto.assign(proto, proto + nargs);
+    for (auto& b : p->proto) b.data = nullptr;
+    node_addref(root);
+    p->root = root;
+    hipGetDevice(&p->device);
+    *out = p;
+    return SKEL_OK;
+}
+
+skel_status skel_plan_run(skel_plan p, const skel_buffer* args, int32_t nargs, void* stream) {
+    clear_error();
+    skel_status st = check_args(p, args, nargs);
+    if (st) return st;
+    if ((st = check_aliasing(p, args))) return st;
+    if ((st = ensure_resources(p))) return st;
+    const hipStream_t s = S(stream);
+    switch (p->lin.dom) {
+        case DOM_U8: return run_image(p, args, s);
+        case DOM_F32: return run_vector(p, args, s);
+        case DOM_NBODY: return run_nbody(p, args, s);
+        default: return set_error(SKEL_EINVAL, "plan has no domain");
+    }
+}
+
+skel_status skel_plan_run_event(skel_plan p, const skel_buffer* args, int32_t nargs, void* stream, void* done) {
+    skel_status st = skel_plan_run(p, args, nargs, stream);
+    if (st) return st;
+    if (done) HIP_TRY(hipEventRecord((hipEvent_t)done, S(stream)));
+    return SKEL_OK;
+}
+
+skel_status skel_plan_describe(skel_plan p, char* buf, size_t len) {
+    clear_error();
+    if (!p || !buf || len == 0) return set_error(SKEL_EINVAL, "null plan or buffer");
+    std::string s = "{\"sct\":\"" + p->lin.sct + "\",\"domain\":\"";
+    s += p->lin.dom == DOM_U8 ? "u8" : (p->lin.dom == DOM_F32 ? "f32" : "nbody");
+    s += "\",\"stages\":[";
+    for (size_t i = 0; i < p->lin.st.size(); ++i) {
+        static const char* nm[] = {"noise", "solarise", "mirror", "blur5", "saxpy", "nbody_force", "leapfrog"};
+        s += (i ? ",\"" : "\"") + std::string(nm[p->lin.st[i].op]) + "\"";
+    }
+    s += "],\"reduce\":";
+    s += p->lin.red < 0 ? "null" : (p->lin.red == SKEL_RED_HIST256_SUM ? "\"hist256_sum\"" : "\"sum\"");
+    char tmp[256];
+    snprintf(tmp, sizeof(tmp), ",\"iterations\":%d,\"loop_carried\":%u,\"loop_sync\":%d,\"kernels\":[",
+             p->lin.nbody_iters, p->lin.loop_carried, p->lin.loop_sync);
+    s += tmp;
+    for (size_t i = 0; i < p->kernels.size(); ++i) {
+        const Kernel& k = p->kernels[i];
+        snprintf(tmp, sizeof(tmp), "%s{\"name\":\"%s\",\"stages\":[%d,%d],\"blur\":%s,\"reduce\":%s,\"grid\":%d,\"wg\":%d}",
+                 i ? "," : "", k.name, k.first, k.last, k.blur ? "true" : "false", k.reduce ? "true" : "false",
+                 k.grid, k.wg);
+        s += tmp;
+    }
+    snprintf(tmp, sizeof(tmp), "],\"config\":{\"fusion\":%d,\"split_mask\":%u,\"tile_h\":%d,\"wg\":%d,\"ept\":%d,\"variant\":%d}}",
+             p->cfg.fusion, p->cfg.split_mask, p->cfg.tile_h, p->cfg.wg, p->cfg.ept, p->cfg.variant);
+    s += tmp;
+    strncpy(buf, s.c_str(), len - 1);
+    buf[len - 1] = 0;
+    return SKEL_OK;
+}
+
+skel_status skel_plan_destroy(skel_plan p) {
+    clear_error();
+    if (!p) return SKEL_OK;
+    for (void* q : p->scratch)
+        if (q) hipFree(q);
+    if (p->partials) hipFree(p->partials);
+    if (p->ticket) hipFree(p->ticket);
+    if (p->nb_acc) hipFree(p->nb_acc);
+    if (p->gexec) hipGraphExecDestroy(p->gexec);
+    if (p->bexec) hipGraphExecDestroy(p->bexec);
+    if (p->cap_stream) hipStreamDestroy(p->cap_stream);
+    if (p->d_reqs) hipFree(p->d_reqs);
+    if (p->d_counter) hipFree(p->d_counter);
+    if (p->h_reqs) hipHostFree(p->h_reqs);
+    node_release(p->root);
+    delete p;
+    return SKEL_OK;
+}
+
+skel_status skel_sync(void* stream) {
+    clear_error();
+    HIP_TRY(hipStreamSynchronize(S(stream)));
+    HIP_TRY(hipGetLastError());
+    return SKEL_OK;
+}
+
+}  // extern "C"

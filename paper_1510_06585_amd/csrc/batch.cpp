@@ -1,0 +1,186 @@
+// Batched execution: many execution requests over data sets that differ in
+// content and size (the batch model of Sec. 2) run as one persistent kernel.
+// The host lays out a work list of wavefront tiles, largest requests first
+// (longest-processing-time order, so the tail of the launch is made of small
+// tiles), and captures [zero outputs, reset ticket, persistent kernel] into a
+// HIP graph that is replayed while the same buffers and shapes come back.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstring>
+#include <numeric>
+
+#include "internal.h"
+
+using namespace skel;
+
+#define HIP_TRY(expr)                                                                          \
+    do {                                                                                       \
+        hipError_t e_ = (expr);                                                                \
+        if (e_ != hipSuccess)                                                                  \
+            return set_error(e_ == hipErrorOutOfMemory ? SKEL_ENOMEM : SKEL_EDEVICE, "%s: %s", \
+                             #expr, hipGetErrorString(e_));                                    \
+    } while (0)
+
+namespace {
+
+skel_status check_req(const skel_buffer* a, int nargs, int red, int r, bool inplace_ok) {
+    for (int k = 0; k < nargs; ++k) {
+        const skel_buffer& b = a[k];
+        for (int d = 0; d < 4; ++d)
+            if (d < b.ndim && b.stride_bytes[d] != 0) {
+                int64_t st = 1;
+                for (int e = d + 1; e < b.ndim; ++e) st *= b.shape[e];
+                const int64_t es = k < 2 ? 1 : (k == 2 && red == SKEL_RED_HIST256_SUM ? 4 : 8);
+                if (b.stride_bytes[d] != st * es && b.shape[d] > 1)
+                    return set_error(SKEL_ESHAPE, "request %d argument %d: not dense", r, k);
+            }
+    }
+    const skel_buffer &in = a[0], &out = a[1];
+    if (in.dtype != SKEL_U8 || out.dtype != SKEL_U8 || in.ndim != 3 || out.ndim != 3 || in.shape[2] != 4 ||
+        out.shape[0] != in.shape[0] || out.shape[1] != in.shape[1] || out.shape[2] != 4)
+        return set_error(SKEL_ESHAPE, "request %d: images must be uint8 [H, W, 4] of equal shape", r);
+    const int64_t H = in.shape[0], W = in.shape[1];
+    if (H < 0 || W < 0 || H > kMaxDim || W > kMaxDim || W * H * 4 >= ((int64_t)1 << 31))
+        return set_error(SKEL_EUNSUPPORTED, "request %d: image of %lld x %lld is out of range", r, (long long)H,
+                         (long long)W);
+    if (W * H > 0 && (!in.data || !out.data)) return set_error(SKEL_EINVAL, "request %d: null image", r);
+    if (in.data == out.data && W * H > 0 && !inplace_ok)
+        return set_error(SKEL_EINVAL, "request %d: in-place run of a kernel with a stencil or a mirror", r);
+    if (red == SKEL_RED_HIST256_SUM) {
+        if (a[2].dtype != SKEL_U32 || a[2].ndim != 2 || a[2].shape[0] != 4 || a[2].shape[1] != 256 || !a[2].data)
+            return set_error(SKEL_ESHAPE, "request %d: hist must be uint32 [4, 256]", r);
+        if (a[3].dtype != SKEL_U64 || a[3].ndim != 1 || a[3].shape[0] != 4 || !a[3].data)
+            return set_error(SKEL_ESHAPE, "request %d: sum must be uint64 [4]", r);
+    } else if (red == SKEL_RED_SUM) {
+        if (a[2].dtype != SKEL_U64 || a[2].ndim != 1 || a[2].shape[0] != 4 || !a[2].data)
+            return set_error(SKEL_ESHAPE, "request %d: sum must be uint64 [4]", r);
+    }
+    return SKEL_OK;
+}
+
+}  // namespace
+
+extern "C" skel_status skel_batch_run(skel_plan p, const skel_buffer* args, int32_t nargs, int32_t nreq,
+                                      void* stream) {
+    clear_error();
+    if (!p) return set_error(SKEL_EINVAL, "null plan");
+    if (p->lin.dom != DOM_U8 || p->kernels.size() != 1)
+        return set_error(SKEL_EUNSUPPORTED, "batched runs need a fully fused image plan (one kernel)");
+    if (nargs != (int32_t)p->proto.size()) return set_error(SKEL_EINVAL, "expected %d arguments per request", (int)p->proto.size());
+    if (nreq < 0 || (nreq > 0 && !args)) return set_error(SKEL_EINVAL, "bad request array");
+    const Kernel& K = p->kernels[0];
+    const int red = p->lin.red;
+    const bool inplace_ok = !(K.blur || K.img.in_flip || K.img.out_flip);
+    for (int r = 0; r < nreq; ++r) {
+        skel_status st = check_req(args + (size_t)r * nargs, nargs, red, r, inplace_ok);
+        if (st) return st;
+    }
+    if (nreq == 0) return SKEL_OK;
+    const hipStream_t s = (hipStream_t)stream;
+    const int tile_h = p->cfg.tile_h;
+    const int bw = K.blur ? kBandOut : kBandPx;
+
+    std::vector<int64_t> key;
+    key.reserve((size_t)nreq * 6);
+    for (int r = 0; r < nreq; ++r) {
+        const skel_buffer* a = args + (size_t)r * nargs;
+        key.push_back((int64_t)(uintptr_t)a[0].data);
+        key.push_back((int64_t)(uintptr_t)a[1].data);
+        key.push_back(nargs > 2 ? (int64_t)(uintptr_t)a[2].data : 0);
+        key.push_back(nargs > 3 ? (int64_t)(uintptr_t)a[3].data : 0);
+        key.push_back(a[0].shape[0]);
+        key.push_back(a[0].shape[1]);
+    }
+    if (p->bexec && key == p->bkey) {
+        HIP_TRY(hipGraphLaunch(p->bexec, s));
+        return SKEL_OK;
+    }
+    // New request set: lay out the work list, largest requests first.
+    std::vector<int> order(nreq);
+    std::iota(order.begin(), order.end(), 0);
+    std::stable_sort(order.begin(), order.end(), [&](int x, int y) {
+        const skel_buffer* a = args + (size_t)x * nargs;
+        const skel_buffer* b = args + (size_t)y * nargs;
+        return a[0].shape[0] * a[0].shape[1] > b[0].shape[0] * b[0].shape[1];
+    });
+    if ((size_t)nreq > p->d_reqs_cap) {
+        // The previous work list may still be in use by queued replays.
+        HIP_TRY(hipStreamSynchronize(s));
+        if (p->d_reqs) hipFree(p->d_reqs);
+        if (p->h_reqs) hipHostFree(p->h_reqs);
+        p->d_reqs = nullptr;
+        p->h_reqs = nullptr;
+        p->d_reqs_cap = 0;
+        HIP_TRY(hipMalloc(&p->d_reqs, sizeof(BatchReq) * nreq));
+        HIP_TRY(hipHostMalloc((void**)&p->h_reqs, sizeof(BatchReq) * nreq, hipHostMallocDefault));
+        p->d_reqs_cap = nreq;
+    }
+    if (!p->d_counter) HIP_TRY(hipMalloc(&p->d_counter, 256));
+    int64_t tiles = 0;
+    for (int k = 0; k < nreq; ++k) {
+        const skel_buffer* a = args + (size_t)order[k] * nargs;
+        BatchReq& R = p->h_reqs[k];
+        memset(&R, 0, sizeof(R));
+        R.in = (const uint8_t*)a[0].data;
+        R.out = (uint8_t*)a[1].data;
+        R.hist = red == SKEL_RED_HIST256_SUM ? (uint32_t*)a[2].data : nullptr;
+        R.sum = red == SKEL_RED_HIST256_SUM ? (uint64_t*)a[3].data : (red == SKEL_RED_SUM ? (uint64_t*)a[2].data : nullptr);
+        R.H = (int32_t)a[0].shape[0];
+        R.W = (int32_t)a[0].shape[1];
+        R.nbands = (R.W + bw - 1) / bw;
+        R.nchunks = (R.H + tile_h - 1) / tile_h;
+        R.tile_begin = (int32_t)tiles;
+        if (R.W > 0 && R.H > 0) tiles += (int64_t)R.nbands * R.nchunks;
+        if (tiles >= ((int64_t)1 << 31)) return set_error(SKEL_EUNSUPPORTED, "batch has too many tiles");
+    }
+    HIP_TRY(hipStreamSynchronize(s));
+    HIP_TRY(hipMemcpy(p->d_reqs, p->h_reqs, sizeof(BatchReq) * nreq, hipMemcpyHostToDevice));
+
+    BatchArgs A;
+    memset(&A, 0, sizeof(A));
+    A.reqs = p->d_reqs;
+    A.nreq = nreq;
+    A.ntiles = (int32_t)tiles;
+    A.tile_h = tile_h;
+    A.has_blur = K.blur;
+    A.in_flip = K.img.in_flip;
+    A.out_flip = K.img.out_flip;
+    A.has_hist = red >= 0;
+    A.counter = p->d_counter;
+    A.pre = K.img.pre;
+    A.post = K.img.post;
+    hipDeviceProp_t prop;
+    HIP_TRY(hipGetDeviceProperties(&prop, p->device));
+    const int wg = K.wg;
+    int per_cu = img_batch_blocks_per_cu(A, wg);
+    if (per_cu < 1) per_cu = 1;
+    int grid = per_cu * prop.multiProcessorCount;
+    const int need = (int)((tiles + wg / 64 - 1) / (wg / 64));
+    grid = std::max(1, std::min(grid, need));
+    p->batch_grid = grid;
+
+    if (p->bexec) {
+        hipGraphExecDestroy(p->bexec);
+        p->bexec = nullptr;
+    }
+    if (!p->cap_stream) HIP_TRY(hipStreamCreateWithFlags(&p->cap_stream, hipStreamNonBlocking));
+    HIP_TRY(hipStreamBeginCapture(p->cap_stream, hipStreamCaptureModeThreadLocal));
+    const char* kname = nullptr;
+    hipError_t e1 = red >= 0 ? launch_batch_zero(p->d_reqs, nreq, p->cap_stream) : hipSuccess;
+    hipError_t e2 = launch_fill_u32(p->d_counter, 1, 0, p->cap_stream);
+    hipError_t e3 = tiles > 0 ? launch_img_batch(A, grid, wg, p->cap_stream, &kname) : hipSuccess;
+    hipGraph_t g = nullptr;
+    hipError_t e4 = hipStreamEndCapture(p->cap_stream, &g);
+    if (e1 || e2 || e3 || e4) {
+        if (g) hipGraphDestroy(g);
+        return set_error(SKEL_EDEVICE, "batch graph capture failed: %s",
+                         hipGetErrorString(e1 ? e1 : (e2 ? e2 : (e3 ? e3 : e4))));
+    }
+    hipError_t e = hipGraphInstantiate(&p->bexec, g, nullptr, nullptr, 0);
+    hipGraphDestroy(g);
+    if (e != hipSuccess) return set_error(SKEL_EDEVICE, "batch graph instantiate failed: %s", hipGetErrorString(e));
+    p->bkey = key;
+    HIP_TRY(hipGraphLaunch(p->bexec, s));
+    return SKEL_OK;
+}

@@ -1,0 +1,133 @@
+// Host-side structures of the skeleton runtime: SCT nodes, the linearised
+// stage chain, compiled plans and their kernels.
+#pragma once
+#include <hip/hip_runtime_api.h>
+
+#include <atomic>
+#include <string>
+#include <vector>
+
+#include "kern.h"
+#include "skel.h"
+
+namespace skel {
+
+enum Domain { DOM_NONE = 0, DOM_U8 = 1, DOM_F32 = 2, DOM_NBODY = 3 };
+enum NodeKind { NK_MAP = 0, NK_PIPE = 1, NK_MAPRED = 2, NK_LOOP = 3 };
+
+constexpr int kMaxStages = 4096;       // linearised Map stages after unrolling loops
+constexpr int kMaxNBodyIters = 4096;   // N-body loop iterations captured in one graph
+constexpr int kMaxDim = 65536;         // image side limit (noise key packs x, y in 16 bits)
+
+// Thread-local error state; set_error returns its status argument.
+skel_status set_error(skel_status st, const char* fmt, ...);
+void clear_error();
+
+}  // namespace skel
+
+struct skel_node_s {
+    std::atomic<int> refs{1};
+    int kind = 0;
+    int op = -1;
+    skel_params prm{};
+    std::vector<skel_node_s*> kids;
+    int red = -1;
+    skel_loop_state loop{};
+};
+
+namespace skel {
+
+struct Stage {
+    int op;            // SKEL_OP_*
+    skel_params prm;
+    int side_arg;      // SAXPY: argument index of its side vector, else -1
+};
+
+// A skeleton tree flattened into depth-first stage order (Sec. 2: the kernels
+// of an SCT run sequentially in a depth-first evaluation of the tree).
+struct Linear {
+    Domain dom = DOM_NONE;
+    std::vector<Stage> st;
+    int red = -1;                 // SKEL_RED_* or -1
+    int nbody_iters = 0;          // Loop(Pipeline(NBODY_FORCE, LEAPFROG)) iterations
+    skel_params nbody_prm{};
+    uint32_t loop_carried = 0;
+    int loop_sync = 0;
+    uint32_t seen_ops = 0;        // bit op: stage kind present in the tree (also in 0-trip loops)
+    std::string sct;              // textual form of the tree
+};
+
+skel_status linearize(skel_node root, Linear& out);
+
+// Resolved configuration (all defaults filled in).
+struct Config {
+    int fusion = SKEL_FUSE_ON;
+    uint32_t split_mask = 0;
+    int tile_h = 0;
+    int wg = 0;
+    int ept = 0;
+    int variant = 0;
+};
+
+// Shape of the arguments a plan is compiled for.
+struct Shape {
+    int64_t W = 0, H = 0;   // images
+    int64_t n = 0;          // vectors
+    int64_t N = 0;          // bodies
+};
+
+// One kernel of a plan.
+struct Kernel {
+    int first = 0, last = 0;   // stage range [first, last); empty = reduce-only
+    bool blur = false;
+    bool reduce = false;
+    int src = 0;               // -1 user input, -2 user output, 0/1 scratch image
+    int dst = 0;               // -2 user output, 0/1 scratch, -3 none
+    ImgGroupArgs img{};        // image kernels (pointers filled per run)
+    VecGroupArgs vec{};        // vector kernels
+    std::vector<int> side_args;
+    int grid = 0, wg = 0;
+    const char* name = "";
+};
+
+skel_status derive_shape(const Linear& lin, const skel_buffer* proto, int32_t nargs, Shape& sh);
+int expected_nargs(const Linear& lin);
+skel_status resolve_config(const Linear& lin, const Shape& sh, const skel_plan_opts* opts, Config& cfg);
+// Builds the kernel list of (lin, sh, cfg); SKEL_EINVAL if the configuration
+// is not valid for this chain (e.g. two stencils forced into one kernel).
+skel_status build_kernels(const Linear& lin, const Shape& sh, const Config& cfg, std::vector<Kernel>& ks);
+// The partition-validity predicate (Sec. 3.1 constraints, adapted): true when
+// the configuration is admissible for this chain and shape.
+bool config_valid(const Linear& lin, const Shape& sh, const Config& cfg);
+
+}  // namespace skel
+
+struct skel_plan_s {
+    skel_node_s* root = nullptr;
+    skel::Linear lin;
+    skel::Shape sh;
+    skel::Config cfg;
+    std::vector<skel_buffer> proto;
+    std::vector<skel::Kernel> kernels;
+    int device = 0;
+    bool resources_ready = false;
+    // plan-owned device memory (allocated on the first run)
+    void* scratch[2] = {nullptr, nullptr};
+    float* partials = nullptr;
+    uint32_t* ticket = nullptr;
+    float4* nb_acc = nullptr;
+    // N-body loop graph
+    hipStream_t cap_stream = nullptr;
+    hipGraphExec_t gexec = nullptr;
+    std::vector<const void*> gkey;
+    // batched execution
+    skel::BatchReq* d_reqs = nullptr;
+    size_t d_reqs_cap = 0;
+    uint32_t* d_counter = nullptr;
+    skel::BatchReq* h_reqs = nullptr;   // pinned host mirror of the work list
+    hipGraphExec_t bexec = nullptr;
+    std::vector<int64_t> bkey;
+    int batch_grid = 0;
+};
+
+skel_status skel_ensure_resources(skel_plan p);

@@ -1,0 +1,133 @@
+// Launch interface between the host runtime (plan/executor) and the gfx950
+// kernels.  Plain structs passed by value as kernel arguments.
+#pragma once
+#include <hip/hip_runtime_api.h>
+#include <stdint.h>
+
+namespace skel {
+
+constexpr int kMaxOps = 8;          // value stages per side of a fused image kernel
+constexpr int kBandOut = 252;       // output pixels per wavefront band (stencil kernels)
+constexpr int kBandPx = 256;        // pixels a wavefront loads per row (64 lanes x 4)
+
+// Value (non-moving) image stages inside a fused kernel.
+enum : uint8_t { IOP_NONE = 0, IOP_NOISE = 1, IOP_SOL = 2 };
+
+// A run of value stages.  flip[k] = 1 when stage k sees the mirrored
+// coordinate W-1-u of the kernel's iteration coordinate u.
+struct OpList {
+    int32_t n;
+    uint8_t op[kMaxOps];
+    uint8_t flip[kMaxOps];
+    uint32_t seed[kMaxOps];
+};
+
+// One fused image kernel: pre-stages, an optional 5x5 blur, post-stages, an
+// optional histogram/sum epilogue.  The kernel iterates over coordinates u of
+// the blur's frame (or of its input, without a blur); it reads the input at
+// in_flip ? W-1-u : u and writes the output at out_flip ? W-1-u : u.
+struct ImgGroupArgs {
+    const uint8_t* in;
+    uint8_t* out;
+    uint32_t* hist;      // [4][256] or null
+    uint64_t* sum;       // [4] or null
+    int32_t W, H;
+    int32_t tile_h;      // rows per tile
+    int32_t nbands;      // tiles across a row
+    int32_t ntiles;      // nbands * ceil(H / tile_h)
+    int32_t in_flip, out_flip;
+    int32_t write_out;   // 0 for a reduce-only kernel
+    OpList pre, post;
+};
+
+// Compile-time encoding of a value-stage run for specialised kernels:
+// sum of op_k * 4^k; -1 selects the generic stage interpreter.
+constexpr int kGeneric = -1;
+int encode_ops(const OpList& l);
+
+// Launches one fused image kernel with `wg` threads per work-group (64, 128
+// or 256).  variant 1 forces the generic interpreter.  *kname receives the
+// kernel's name.
+hipError_t launch_img_group(const ImgGroupArgs& a, bool blur, bool hist, int wg, int variant,
+                            hipStream_t s, const char** kname);
+
+const char* img_kernel_name(const ImgGroupArgs& a, bool blur, bool hist, int variant);
+
+// Work list entry of the batched persistent kernel (one per request).
+struct BatchReq {
+    const uint8_t* in;
+    uint8_t* out;
+    uint32_t* hist;
+    uint64_t* sum;
+    int32_t W, H;
+    int32_t nbands, nchunks;
+    int32_t tile_begin;  // first global tile index of this request
+    int32_t pad;
+};
+struct BatchArgs {
+    const BatchReq* reqs;
+    int32_t nreq;
+    int32_t ntiles;
+    int32_t tile_h;
+    int32_t has_blur;
+    int32_t in_flip, out_flip;
+    int32_t has_hist;
+    uint32_t* counter;   // work-queue ticket counter (zeroed before launch)
+    OpList pre, post;
+};
+hipError_t launch_img_batch(const BatchArgs& a, int grid, int wg, hipStream_t s, const char** kname);
+hipError_t launch_batch_zero(const BatchReq* reqs, int nreq, hipStream_t s);
+// Resident work-groups per CU of the persistent kernel for this chain.
+int img_batch_blocks_per_cu(const BatchArgs& a, int wg);
+
+// Fill kernel (graph-safe replacement of memset): n 32-bit words of `value`.
+hipError_t launch_fill_u32(void* p, uint64_t nwords, uint32_t value, hipStream_t s);
+
+// ---------------------------------------------------------------- fp32 chains
+constexpr int kMaxVecOps = 8;
+struct VecGroupArgs {
+    const float* in;
+    float* out;
+    int64_t n;
+    int32_t nops;
+    int32_t in_flip, out_flip;
+    int32_t ept;              // 4-float vectors per thread
+    float* partials;          // per work-group partial sums (reduce) or null
+    uint32_t* ticket;         // completion counter for the final reduction
+    float* sum_out;           // final sum or null
+    int32_t write_out;
+    int32_t pad;
+    const float* side[kMaxVecOps];
+    float a[kMaxVecOps];
+    uint8_t flip[kMaxVecOps];
+};
+hipError_t launch_vec_group(const VecGroupArgs& a, int grid, int wg, hipStream_t s, const char** kname);
+
+// -------------------------------------------------------------------- N-body
+struct NBodyArgs {
+    const float4* pos_in;   // [N] x,y,z,m
+    float4* pos_out;        // [N]
+    float4* vel;            // [N] (w unused), updated in place
+    float4* acc;            // [N] accelerations (unfused force kernel) or null
+    int32_t N;
+    int32_t jsplit;         // wavefronts sharing one group of 64 bodies
+    float eps2, G, dt;
+    int32_t pad;
+};
+// Fused force + kick-drift (fused = true) or force only into acc.
+hipError_t launch_nbody_force(const NBodyArgs& a, bool fused, hipStream_t s, const char** kname);
+hipError_t launch_nbody_integrate(const NBodyArgs& a, hipStream_t s, const char** kname);
+hipError_t launch_copy_f32x4(const float4* src, float4* dst, int64_t n, hipStream_t s);
+
+// ------------------------------------------------------------------- MLP
+hipError_t launch_mlp_forward(const float* params, const float* X, int n, float* y, hipStream_t s);
+hipError_t launch_mlp_grad(const float* params, const float* X, const float* t, int n, float* grad,
+                           float* loss, float* work, hipStream_t s);
+// As launch_mlp_grad over the samples idx[0..n) of X / t (idx may be null).
+hipError_t launch_mlp_grad_idx(const float* params, const float* X, const float* t, const int* idx, int n,
+                               float* grad, float* loss, float* work, hipStream_t s);
+hipError_t launch_mlp_adam(float* params, const float* grad, float* m, float* v, int step, float lr,
+                           float b1, float b2, float eps, hipStream_t s);
+size_t mlp_grad_work_floats(int n);
+
+}  // namespace skel

@@ -1,0 +1,499 @@
+// Plan compiler: linearises a skeleton tree, checks its typing, resolves the
+// execution configuration and groups adjacent Map stages into fused kernels.
+//
+// Fusion follows the paper's locality-aware decomposition (Sec. 3.1): kernels
+// that pass data to each other must see the same partitioning so the data can
+// stay where it is.  On one GPU the strongest form of that rule is to run the
+// communicating stages in one kernel over one tile, so intermediates never
+// leave registers.  A mirror is a pixel permutation within a line; inside a
+// fused kernel it becomes a coordinate flip of the stages around it.
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+
+#include "internal.h"
+
+namespace skel {
+
+static thread_local std::string g_err;
+
+skel_status set_error(skel_status st, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return st;
+}
+void clear_error() { g_err.clear(); }
+const char* last_error_str() { return g_err.c_str(); }
+
+static const char* op_name(int op) {
+    switch (op) {
+        case SKEL_OP_NOISE: return "noise";
+        case SKEL_OP_SOLARISE: return "solarise";
+        case SKEL_OP_MIRROR: return "mirror";
+        case SKEL_OP_BLUR5: return "blur5";
+        case SKEL_OP_SAXPY: return "saxpy";
+        case SKEL_OP_NBODY_FORCE: return "nbody_force";
+        case SKEL_OP_LEAPFROG: return "leapfrog";
+    }
+    return "?";
+}
+
+static skel_status lin_rec(const skel_node_s* n, Linear& L, bool root, int depth) {
+    if (!n) return set_error(SKEL_EINVAL, "null node in skeleton tree");
+    if (depth > 64) return set_error(SKEL_EINVAL, "skeleton tree deeper than 64 levels");
+    switch (n->kind) {
+        case NK_MAP:
+            if ((int)L.st.size() >= kMaxStages)
+                return set_error(SKEL_EUNSUPPORTED, "more than %d stages after unrolling loops", kMaxStages);
+            L.st.push_back(Stage{n->op, n->prm, -1});
+            L.seen_ops |= 1u << n->op;
+            L.sct += op_name(n->op);
+            return SKEL_OK;
+        case NK_PIPE: {
+            L.sct += "pipeline(";
+            for (size_t k = 0; k < n->kids.size(); ++k) {
+                if (k) L.sct += ",";
+                skel_status st = lin_rec(n->kids[k], L, false, depth + 1);
+                if (st) return st;
+            }
+            L.sct += ")";
+            return SKEL_OK;
+        }
+        case NK_LOOP: {
+            Linear body;
+            skel_status st = lin_rec(n->kids[0], body, false, depth + 1);
+            if (st) return st;
+            const int it = n->loop.iterations;
+            if ((int64_t)body.st.size() * it + (int64_t)L.st.size() > (int64_t)kMaxStages * 2)
+                return set_error(SKEL_EUNSUPPORTED, "loop unrolls to more than %d stages", 2 * kMaxStages);
+            for (int r = 0; r < it; ++r) L.st.insert(L.st.end(), body.st.begin(), body.st.end());
+            L.seen_ops |= body.seen_ops;
+            if (it == 0 && (body.seen_ops & ((1u << SKEL_OP_NBODY_FORCE) | (1u << SKEL_OP_LEAPFROG)))) {
+                // keep the N-body parameters of a zero-trip loop's body
+                for (const Stage& b : body.st) {
+                    if (b.op == SKEL_OP_NBODY_FORCE) L.nbody_prm.eps = b.prm.eps, L.nbody_prm.G = b.prm.G;
+                    if (b.op == SKEL_OP_LEAPFROG) L.nbody_prm.dt = b.prm.dt;
+                }
+            }
+            L.loop_carried |= n->loop.carried_mask;
+            L.loop_sync |= n->loop.global_sync;
+            char buf[32];
+            snprintf(buf, sizeof(buf), "loop[%d](", it);
+            L.sct += buf;
+            L.sct += body.sct;
+            L.sct += ")";
+            return SKEL_OK;
+        }
+        case NK_MAPRED: {
+            if (!root) return set_error(SKEL_EINVAL, "MapReduce is only valid at the root of a plan");
+            L.sct += "mapreduce(";
+            skel_status st = lin_rec(n->kids[0], L, false, depth + 1);
+            if (st) return st;
+            L.red = n->red;
+            L.sct += n->red == SKEL_RED_HIST256_SUM ? ",hist256_sum)" : ",sum)";
+            return SKEL_OK;
+        }
+    }
+    return set_error(SKEL_EINVAL, "unknown node kind");
+}
+
+skel_status linearize(skel_node root, Linear& L) {
+    L = Linear();
+    skel_status st = lin_rec(root, L, true, 0);
+    if (st) return st;
+    auto has = [&](int op) { return (L.seen_ops >> op) & 1u; };
+    const int img = has(SKEL_OP_NOISE) + has(SKEL_OP_SOLARISE) + has(SKEL_OP_BLUR5);
+    const int vec = has(SKEL_OP_SAXPY);
+    const int nb = has(SKEL_OP_NBODY_FORCE) + has(SKEL_OP_LEAPFROG);
+    if (nb) {
+        if (img || vec || has(SKEL_OP_MIRROR) || L.red >= 0 || (L.st.size() % 2) != 0)
+            return set_error(SKEL_ETYPE, "N-body stages must form Pipeline(nbody_force, leapfrog), optionally looped");
+        for (size_t k = 0; k < L.st.size(); k += 2) {
+            const Stage& f = L.st[k];
+            const Stage& g = L.st[k + 1];
+            if (f.op != SKEL_OP_NBODY_FORCE || g.op != SKEL_OP_LEAPFROG)
+                return set_error(SKEL_ETYPE, "N-body stages must alternate nbody_force, leapfrog");
+            if (f.prm.eps != L.st[0].prm.eps || f.prm.G != L.st[0].prm.G || g.prm.dt != L.st[1].prm.dt)
+                return set_error(SKEL_EUNSUPPORTED, "N-body parameters differ between iterations");
+        }
+        L.dom = DOM_NBODY;
+        L.nbody_iters = (int)(L.st.size() / 2);
+        if (L.nbody_iters > kMaxNBodyIters)
+            return set_error(SKEL_EUNSUPPORTED, "N-body loop of more than %d iterations", kMaxNBodyIters);
+        if (!L.st.empty()) {
+            L.nbody_prm = L.st[0].prm;
+            L.nbody_prm.dt = L.st[1].prm.dt;
+        }
+        if (L.st.size() > 2) L.st.resize(2);   // one (force, kick-drift) step; the Loop driver repeats it
+        return SKEL_OK;
+    }
+    if (img && vec) return set_error(SKEL_ETYPE, "image stages and fp32 vector stages cannot share a chain");
+    L.dom = img ? DOM_U8 : (vec ? DOM_F32 : DOM_NONE);
+    if (L.dom == DOM_F32 && L.red == SKEL_RED_HIST256_SUM)
+        return set_error(SKEL_ETYPE, "the histogram reduce applies to RGBA uint8 images only");
+    int k = 0;
+    for (Stage& s : L.st)
+        if (s.op == SKEL_OP_SAXPY) s.side_arg = 1 + k++;
+    return SKEL_OK;
+}
+
+int expected_nargs(const Linear& L) {
+    if (L.dom == DOM_NBODY) return 3;
+    if (L.dom == DOM_U8) return 2 + (L.red == SKEL_RED_HIST256_SUM ? 2 : (L.red == SKEL_RED_SUM ? 1 : 0));
+    if (L.dom == DOM_F32) {
+        int ns = 0;
+        for (const Stage& s : L.st) ns += s.op == SKEL_OP_SAXPY;
+        return 2 + ns + (L.red >= 0 ? 1 : 0);
+    }
+    return 2;
+}
+
+static bool dense_ok(const skel_buffer& b, int64_t esize) {
+    int64_t stride = esize;
+    for (int d = b.ndim - 1; d >= 0; --d) {
+        if (b.stride_bytes[d] != 0 && b.stride_bytes[d] != stride && b.shape[d] > 1) return false;
+        stride *= b.shape[d];
+    }
+    return true;
+}
+
+static int64_t dtype_size(int dt) {
+    switch (dt) {
+        case SKEL_U8: return 1;
+        case SKEL_U32: return 4;
+        case SKEL_U64: return 8;
+        case SKEL_F32: return 4;
+        case SKEL_F64: return 8;
+    }
+    return 0;
+}
+
+static skel_status check_buf(const skel_buffer& b, int k, int dt, int ndim, const int64_t* shape) {
+    if (b.dtype != dt) return set_error(SKEL_ETYPE, "argument %d: dtype %d, expected %d", k, b.dtype, dt);
+    if (b.ndim != ndim) return set_error(SKEL_ESHAPE, "argument %d: %d dims, expected %d", k, b.ndim, ndim);
+    for (int d = 0; d < ndim; ++d)
+        if (shape[d] >= 0 && b.shape[d] != shape[d])
+            return set_error(SKEL_ESHAPE, "argument %d: dim %d is %lld, expected %lld", k, d, (long long)b.shape[d],
+                             (long long)shape[d]);
+    for (int d = 0; d < ndim; ++d)
+        if (b.shape[d] < 0) return set_error(SKEL_ESHAPE, "argument %d: negative extent", k);
+    if (!dense_ok(b, dtype_size(dt))) return set_error(SKEL_ESHAPE, "argument %d: not dense row-major", k);
+    return SKEL_OK;
+}
+
+skel_status derive_shape(const Linear& L, const skel_buffer* proto, int32_t nargs, Shape& sh) {
+    sh = Shape();
+    if (nargs != expected_nargs(L))
+        return set_error(SKEL_EINVAL, "expected %d arguments, got %d", expected_nargs(L), nargs);
+    skel_status st;
+    if (L.dom == DOM_U8) {
+        const int64_t H = proto[0].shape[0], W = proto[0].shape[1];
+        const int64_t img[3] = {H, W, 4};
+        if ((st = check_buf(proto[0], 0, SKEL_U8, 3, img))) return st;
+        if ((st = check_buf(proto[1], 1, SKEL_U8, 3, img))) return st;
+        if (L.red == SKEL_RED_HIST256_SUM) {
+            const int64_t hs[2] = {4, 256}, ss[1] = {4};
+            if ((st = check_buf(proto[2], 2, SKEL_U32, 2, hs))) return st;
+            if ((st = check_buf(proto[3], 3, SKEL_U64, 1, ss))) return st;
+        } else if (L.red == SKEL_RED_SUM) {
+            const int64_t ss[1] = {4};
+            if ((st = check_buf(proto[2], 2, SKEL_U64, 1, ss))) return st;
+        }
+        if (W > kMaxDim || H > kMaxDim)
+            return set_error(SKEL_EUNSUPPORTED, "image sides are limited to %d pixels", kMaxDim);
+        if (W * H * 4 >= ((int64_t)1 << 31)) return set_error(SKEL_EUNSUPPORTED, "images are limited to 2 GiB");
+        sh.W = W;
+        sh.H = H;
+        return SKEL_OK;
+    }
+    if (L.dom == DOM_F32) {
+        const int64_t n = proto[0].shape[0];
+        const int64_t vs[1] = {n};
+        for (int k = 0; k < nargs - (L.red >= 0 ? 1 : 0); ++k)
+            if ((st = check_buf(proto[k], k, SKEL_F32, 1, vs))) return st;
+        if (L.red >= 0) {
+            const int64_t one[1] = {1};
+            if ((st = check_buf(proto[nargs - 1], nargs - 1, SKEL_F32, 1, one))) return st;
+        }
+        if (n * 4 >= ((int64_t)1 << 31)) return set_error(SKEL_EUNSUPPORTED, "vectors are limited to 2 GiB");
+        sh.n = n;
+        return SKEL_OK;
+    }
+    if (L.dom == DOM_NBODY) {
+        const int64_t N = proto[0].shape[0];
+        const int64_t bs[2] = {N, 4};
+        for (int k = 0; k < 3; ++k)
+            if ((st = check_buf(proto[k], k, SKEL_F32, 2, bs))) return st;
+        if (N > (1 << 24)) return set_error(SKEL_EUNSUPPORTED, "at most 2^24 bodies");
+        sh.N = N;
+        return SKEL_OK;
+    }
+    return set_error(SKEL_ETYPE, "cannot tell the domain of the chain");
+}
+
+static int pow2_floor(int64_t v) {
+    int p = 1;
+    while ((int64_t)p * 2 <= v) p *= 2;
+    return p;
+}
+
+skel_status resolve_config(const Linear& L, const Shape& sh, const skel_plan_opts* o, Config& c) {
+    c = Config();
+    skel_plan_opts d;
+    skel_plan_opts_default(&d);
+    if (!o) o = &d;
+    c.fusion = o->fusion == SKEL_FUSE_AUTO ? SKEL_FUSE_ON : o->fusion;
+    if (c.fusion < SKEL_FUSE_OFF || c.fusion > SKEL_FUSE_MASK) return set_error(SKEL_EINVAL, "bad fusion mode");
+    c.split_mask = o->split_mask;
+    c.variant = o->variant;
+    if (c.variant < 0 || c.variant > 1) return set_error(SKEL_EINVAL, "variant must be 0 or 1");
+    if (L.dom == DOM_U8) {
+        c.wg = o->wg ? o->wg : 256;
+        if (c.wg != 64 && c.wg != 128 && c.wg != 256) return set_error(SKEL_EINVAL, "image kernels take wg 64, 128 or 256");
+        if (o->tile_h) {
+            c.tile_h = o->tile_h;
+        } else {
+            bool blur = false;
+            for (const Stage& s : L.st) blur |= s.op == SKEL_OP_BLUR5;
+            const int64_t nb = (sh.W + (blur ? kBandOut : kBandPx) - 1) / (blur ? kBandOut : kBandPx);
+            // Enough wavefront tiles to fill 256 CUs several times over.
+            int th = 256;
+            while (th > (blur ? 16 : 8) && nb * ((sh.H + th - 1) / th) < 4096) th /= 2;
+            c.tile_h = th;
+        }
+        if (c.tile_h < 1 || c.tile_h > kMaxDim) return set_error(SKEL_EINVAL, "tile_h out of range");
+        c.ept = 1;
+    } else if (L.dom == DOM_F32) {
+        c.wg = o->wg ? o->wg : 256;
+        if (c.wg < 64 || c.wg > 1024 || c.wg % 64) return set_error(SKEL_EINVAL, "wg must be a multiple of 64 up to 1024");
+        const int64_t nvec = (sh.n + 3) / 4;
+        c.ept = o->ept ? o->ept : (nvec >= ((int64_t)1 << 20) ? 4 : 1);
+        if (c.ept < 1 || c.ept > 64) return set_error(SKEL_EINVAL, "ept out of range");
+        c.tile_h = 0;
+    } else if (L.dom == DOM_NBODY) {
+        c.tile_h = o->tile_h ? o->tile_h : 4;
+        if (c.tile_h < 1 || c.tile_h > 16) return set_error(SKEL_EINVAL, "N-body j-slices must be 1..16");
+        c.wg = 64 * c.tile_h;
+        c.ept = 1;
+        (void)pow2_floor;
+    }
+    return SKEL_OK;
+}
+
+// Segments [first, last) of a chain of k stages under the fusion mode.
+static skel_status segments(const Linear& L, const Config& c, std::vector<std::pair<int, int>>& segs, bool& red_sep) {
+    const int k = (int)L.st.size();
+    segs.clear();
+    red_sep = false;
+    if (k == 0) {
+        segs.push_back({0, 0});
+        return SKEL_OK;
+    }
+    auto is_stencil = [&](int i) { return L.st[i].op == SKEL_OP_BLUR5; };
+    auto is_value = [&](int i) { return L.st[i].op == SKEL_OP_NOISE || L.st[i].op == SKEL_OP_SOLARISE || L.st[i].op == SKEL_OP_SAXPY; };
+    if (c.fusion == SKEL_FUSE_OFF) {
+        for (int i = 0; i < k; ++i) segs.push_back({i, i + 1});
+        red_sep = L.red >= 0;
+        return SKEL_OK;
+    }
+    if (c.fusion == SKEL_FUSE_ON) {
+        int start = 0, nst = 0, nval_pre = 0, nval_post = 0;
+        for (int i = 0; i < k; ++i) {
+            bool cut = false;
+            if (is_stencil(i) && nst == 1) cut = true;
+            if (is_value(i) && ((nst == 0 ? nval_pre : nval_post) >= kMaxOps)) cut = true;
+            if (cut) {
+                segs.push_back({start, i});
+                start = i;
+                nst = nval_pre = nval_post = 0;
+            }
+            if (is_stencil(i)) nst++;
+            if (is_value(i)) (nst == 0 ? nval_pre : nval_post)++;
+        }
+        segs.push_back({start, k});
+        return SKEL_OK;
+    }
+    // SKEL_FUSE_MASK
+    int start = 0;
+    for (int i = 0; i < k - 1; ++i)
+        if (c.split_mask & (1u << i)) {
+            segs.push_back({start, i + 1});
+            start = i + 1;
+        }
+    segs.push_back({start, k});
+    red_sep = L.red >= 0 && (c.split_mask & (1u << (k - 1)));
+    if (L.red < 0 && (c.split_mask >> (k - 1)) != 0 && k <= 32)
+        return set_error(SKEL_EINVAL, "split_mask has bits beyond the chain");
+    for (auto& s : segs) {
+        int nst = 0, pre = 0, post = 0;
+        for (int i = s.first; i < s.second; ++i) {
+            if (is_stencil(i)) nst++;
+            if (is_value(i)) (nst == 0 ? pre : post)++;
+        }
+        if (nst > 1) return set_error(SKEL_EINVAL, "split_mask puts two stencil stages in one kernel");
+        if (pre > kMaxOps || post > kMaxOps) return set_error(SKEL_EINVAL, "more than %d value stages in one kernel", kMaxOps);
+    }
+    return SKEL_OK;
+}
+
+static void push_op(OpList& l, const Stage& s, int flip) {
+    const int k = l.n++;
+    l.op[k] = s.op == SKEL_OP_NOISE ? IOP_NOISE : IOP_SOL;
+    l.flip[k] = (uint8_t)(flip & 1);
+    l.seed[k] = s.prm.seed;
+}
+
+skel_status build_kernels(const Linear& L, const Shape& sh, const Config& c, std::vector<Kernel>& ks) {
+    ks.clear();
+    if (L.dom == DOM_NBODY) {
+        Kernel k;
+        k.first = 0;
+        k.last = 2;
+        k.wg = c.wg;
+        k.grid = (int)((sh.N + 63) / 64);
+        k.name = c.fusion == SKEL_FUSE_OFF ? "nbody_force" : "nbody_force_kick_drift";
+        ks.push_back(k);
+        if (c.fusion == SKEL_FUSE_OFF) {
+            Kernel g = k;
+            g.first = 1;
+            g.name = "nbody_kick_drift";
+            ks.push_back(g);
+        }
+        return SKEL_OK;
+    }
+    std::vector<std::pair<int, int>> segs;
+    bool red_sep = false;
+    skel_status st = segments(L, c, segs, red_sep);
+    if (st) return st;
+    const int nk = (int)segs.size();
+    for (int g = 0; g < nk; ++g) {
+        Kernel K;
+        K.first = segs[g].first;
+        K.last = segs[g].second;
+        K.src = g == 0 ? -1 : ((g - 1) % 2);
+        K.dst = g == nk - 1 ? -2 : (g % 2);
+        K.reduce = (g == nk - 1) && L.red >= 0 && !red_sep;
+        K.wg = c.wg;
+        if (L.dom == DOM_U8 || L.dom == DOM_NONE) {
+            int b = -1;
+            for (int i = K.first; i < K.last; ++i)
+                if (L.st[i].op == SKEL_OP_BLUR5) b = i;
+            ImgGroupArgs& A = K.img;
+            memset(&A, 0, sizeof(A));
+            auto mirrors = [&](int lo, int hi) {
+                int m = 0;
+                for (int i = lo; i < hi; ++i) m += L.st[i].op == SKEL_OP_MIRROR;
+                return m & 1;
+            };
+            if (b >= 0) {
+                K.blur = true;
+                A.in_flip = mirrors(K.first, b);
+                A.out_flip = mirrors(b + 1, K.last);
+                for (int i = K.first; i < b; ++i)
+                    if (L.st[i].op == SKEL_OP_NOISE || L.st[i].op == SKEL_OP_SOLARISE) push_op(A.pre, L.st[i], mirrors(i + 1, b));
+                for (int i = b + 1; i < K.last; ++i)
+                    if (L.st[i].op == SKEL_OP_NOISE || L.st[i].op == SKEL_OP_SOLARISE) push_op(A.post, L.st[i], mirrors(b + 1, i));
+            } else {
+                A.in_flip = 0;
+                A.out_flip = mirrors(K.first, K.last);
+                for (int i = K.first; i < K.last; ++i)
+                    if (L.st[i].op == SKEL_OP_NOISE || L.st[i].op == SKEL_OP_SOLARISE) push_op(A.pre, L.st[i], mirrors(K.first, i));
+            }
+            A.W = (int32_t)sh.W;
+            A.H = (int32_t)sh.H;
+            A.tile_h = c.tile_h;
+            const int bw = K.blur ? kBandOut : kBandPx;
+            A.nbands = (int32_t)((sh.W + bw - 1) / bw);
+            const int64_t chunks = (sh.H + c.tile_h - 1) / c.tile_h;
+            A.ntiles = (sh.W == 0 || sh.H == 0) ? 0 : (int32_t)(A.nbands * chunks);
+            A.write_out = 1;
+            K.grid = (A.ntiles + c.wg / 64 - 1) / (c.wg / 64);
+            K.name = img_kernel_name(A, K.blur, K.reduce, c.variant);
+        } else {
+            VecGroupArgs& A = K.vec;
+            memset(&A, 0, sizeof(A));
+            int m = 0;
+            for (int i = K.first; i < K.last; ++i) {
+                if (L.st[i].op == SKEL_OP_MIRROR) {
+                    m ^= 1;
+                } else {
+                    if (A.nops >= kMaxVecOps) return set_error(SKEL_EINVAL, "more than %d saxpy stages in one kernel", kMaxVecOps);
+                    A.a[A.nops] = L.st[i].prm.a;
+                    A.flip[A.nops] = (uint8_t)m;
+                    K.side_args.push_back(L.st[i].side_arg);
+                    A.nops++;
+                }
+            }
+            A.out_flip = m;
+            A.n = sh.n;
+            A.ept = c.ept;
+            A.write_out = 1;
+            const int64_t nvec = (sh.n + 3) / 4;
+            K.grid = (int)((nvec + (int64_t)c.wg * c.ept - 1) / ((int64_t)c.wg * c.ept));
+            K.name = "vec_chain";
+        }
+        ks.push_back(K);
+    }
+    if (red_sep) {
+        Kernel R;
+        R.first = R.last = (int)L.st.size();
+        R.src = -2;
+        R.dst = -3;
+        R.reduce = true;
+        R.wg = c.wg;
+        if (L.dom == DOM_U8) {
+            ImgGroupArgs& A = R.img;
+            memset(&A, 0, sizeof(A));
+            A.W = (int32_t)sh.W;
+            A.H = (int32_t)sh.H;
+            A.tile_h = c.tile_h;
+            A.nbands = (int32_t)((sh.W + kBandPx - 1) / kBandPx);
+            const int64_t chunks = (sh.H + c.tile_h - 1) / c.tile_h;
+            A.ntiles = (sh.W == 0 || sh.H == 0) ? 0 : (int32_t)(A.nbands * chunks);
+            A.write_out = 0;
+            R.grid = (A.ntiles + c.wg / 64 - 1) / (c.wg / 64);
+            R.name = img_kernel_name(A, false, true, c.variant);
+        } else {
+            VecGroupArgs& A = R.vec;
+            memset(&A, 0, sizeof(A));
+            A.n = sh.n;
+            A.ept = c.ept;
+            A.write_out = 0;
+            const int64_t nvec = (sh.n + 3) / 4;
+            R.grid = (int)((nvec + (int64_t)c.wg * c.ept - 1) / ((int64_t)c.wg * c.ept));
+            R.name = "vec_chain";
+        }
+        ks.push_back(R);
+    }
+    return SKEL_OK;
+}
+
+bool config_valid(const Linear& L, const Shape& sh, const Config& c) {
+    std::vector<Kernel> ks;
+    std::string saved = g_err;
+    const bool ok = build_kernels(L, sh, c, ks) == SKEL_OK;
+    g_err = saved;
+    if (!ok) return false;
+    if (L.dom == DOM_U8) {
+        // Partitioning constraints (Sec. 3.1): a tile's rows times the 4 pixels
+        // each lane computes must divide evenly into work-groups of wg/64 tiles;
+        // here every tile is one wavefront, so wg must be a multiple of 64 and
+        // a work-group may not span fewer than one tile.
+        if (c.wg % 64 || c.tile_h < 1) return false;
+    }
+    return true;
+}
+
+}  // namespace skel
+
+extern "C" const char* skel_last_error(void) { return skel::last_error_str(); }
+
+extern "C" void skel_plan_opts_default(skel_plan_opts* o) {
+    if (!o) return;
+    memset(o, 0, sizeof(*o));
+    o->fusion = SKEL_FUSE_ON;
+}

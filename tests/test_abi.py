@@ -1,0 +1,172 @@
+"""Host-side checks of the C-ABI library: it loads, exports every declared
+symbol, builds and linearises skeleton trees, groups stages into kernels and
+rejects malformed requests -- all without a GPU (plan compilation is
+host-only; device resources are allocated by a plan's first run)."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import paper_1510_06585_amd as sk
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _ensure_built():
+    if not os.path.exists(sk.skel.LIB_PATH):
+        from paper_1510_06585_amd import build
+        build.build()
+
+
+_ensure_built()
+
+
+def declared_symbols():
+    src = open(os.path.join(ROOT, "include", "skel.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(skel_[a-z0-9_]+)\s*\(", src)))
+
+
+def test_library_exports_every_declared_symbol():
+    names = declared_symbols()
+    assert len(names) >= 20
+    L = ctypes.CDLL(sk.skel.LIB_PATH)
+    for n in names:
+        assert hasattr(L, n), n
+    assert set(names) == set(sk.skel.EXPORTS)
+
+
+def img(H, W):
+    return [sk.proto([H, W, 4], sk.U8), sk.proto([H, W, 4], sk.U8)]
+
+
+def hist_args(H, W):
+    return img(H, W) + [sk.proto([4, 256], sk.U32), sk.proto([4], sk.U64)]
+
+
+CFG2 = [("noise", {"seed": 0x1510}), ("solarise", {}), ("blur5", {}), ("mirror", {})]
+
+
+def test_fused_config2_is_one_kernel_with_mirror_on_the_store():
+    p = sk.Plan(sk.image_chain(CFG2, "hist_sum"), hist_args(64, 100))
+    d = p.describe()
+    assert d["stages"] == ["noise", "solarise", "blur5", "mirror"]
+    assert len(d["kernels"]) == 1
+    k = d["kernels"][0]
+    assert k["blur"] and k["reduce"] and k["name"] == "img_noise_sol_blur_reduce"
+
+
+def test_unfused_is_one_kernel_per_stage_in_depth_first_order():
+    # Sec. 2: pipeline(K1, loop(K2), K3) runs K1, then K2 n times, then K3.
+    root = sk.MapReduce(sk.Pipeline(sk.Map("noise", seed=1), sk.Loop(sk.Map("blur5"), 3), sk.Map("mirror")),
+                        sk.RED_HIST256_SUM)
+    p = sk.Plan(root, hist_args(16, 16), {"fusion": sk.FUSE_OFF})
+    d = p.describe()
+    assert d["stages"] == ["noise", "blur5", "blur5", "blur5", "mirror"]
+    assert [k["stages"] for k in d["kernels"]] == [[0, 1], [1, 2], [2, 3], [3, 4], [4, 5], [5, 5]]
+    assert d["kernels"][-1]["reduce"] and not d["kernels"][-2]["reduce"]
+    assert d["sct"] == "mapreduce(pipeline(noise,loop[3](blur5),mirror),hist256_sum)"
+
+
+def test_fusion_splits_at_second_stencil():
+    root = sk.image_chain([("noise", {"seed": 1}), ("blur5", {}), ("solarise", {}), ("blur5", {}), ("mirror", {})])
+    d = sk.Plan(root, img(32, 300)).describe()
+    assert [k["stages"] for k in d["kernels"]] == [[0, 3], [3, 5]]
+
+
+def test_split_mask_partitions_and_rejects_two_stencils():
+    root = sk.image_chain(CFG2, "hist_sum")
+    d = sk.Plan(root, hist_args(8, 8), {"fusion": sk.FUSE_MASK, "split_mask": 0b0010}).describe()
+    assert [k["stages"] for k in d["kernels"]] == [[0, 2], [2, 4]]
+    d = sk.Plan(root, hist_args(8, 8), {"fusion": sk.FUSE_MASK, "split_mask": 0b1000}).describe()
+    assert [k["stages"] for k in d["kernels"]] == [[0, 4], [4, 4]] and d["kernels"][1]["reduce"]
+    two = sk.image_chain([("blur5", {}), ("blur5", {})])
+    with pytest.raises(sk.SkelError) as e:
+        sk.Plan(two, img(8, 8), {"fusion": sk.FUSE_MASK, "split_mask": 0})
+    assert e.value.status == sk.EINVAL
+
+
+def test_generic_variant_selected_on_request():
+    root = sk.image_chain(CFG2, "hist_sum")
+    d = sk.Plan(root, hist_args(8, 8), {"variant": 1}).describe()
+    assert d["kernels"][0]["name"] == "img_generic_blur_reduce"
+
+
+def test_type_and_shape_errors():
+    with pytest.raises(sk.SkelError) as e:
+        sk.Plan(sk.Pipeline(sk.Map("noise"), sk.Map("saxpy", a=1.0)), img(4, 4))
+    assert e.value.status == sk.ETYPE
+    with pytest.raises(sk.SkelError) as e:
+        sk.Plan(sk.image_chain(CFG2, "hist_sum"), img(4, 4))          # missing reduce outputs
+    assert e.value.status == sk.EINVAL
+    with pytest.raises(sk.SkelError) as e:
+        sk.Plan(sk.image_chain(CFG2), [sk.proto([4, 4, 4], sk.U8), sk.proto([4, 5, 4], sk.U8)])
+    assert e.value.status == sk.ESHAPE
+    with pytest.raises(sk.SkelError) as e:
+        sk.Plan(sk.image_chain(CFG2), img(2, 65537))
+    assert e.value.status == sk.EUNSUPPORTED
+    with pytest.raises(sk.SkelError) as e:
+        sk.Plan(sk.MapReduce(sk.Map("saxpy", a=1.0), sk.RED_HIST256_SUM),
+                [sk.proto([8], sk.F32)] * 3 + [sk.proto([1], sk.F32)])
+    assert e.value.status == sk.ETYPE
+    with pytest.raises(sk.SkelError) as e:      # MapReduce below the root
+        sk.Pipeline(sk.MapReduce(sk.Map("noise"), sk.RED_SUM), sk.Map("mirror"))
+        sk.Loop(sk.MapReduce(sk.Map("noise"), sk.RED_SUM), 2)
+    assert e.value.status == sk.EINVAL
+    with pytest.raises(sk.SkelError) as e:
+        sk.Map(99)
+    assert e.value.status == sk.EINVAL
+    with pytest.raises(sk.SkelError):
+        sk.Plan(sk.image_chain(CFG2), img(8, 8), {"wg": 96})
+
+
+def test_nbody_structure_checks():
+    p = sk.Plan(sk.nbody_loop(20), [sk.proto([128, 4], sk.F32)] * 3)
+    d = p.describe()
+    assert d["iterations"] == 20 and d["kernels"][0]["name"] == "nbody_force_kick_drift"
+    assert d["loop_sync"] == 1 and d["loop_carried"] == 0b011
+    d = sk.Plan(sk.nbody_loop(3), [sk.proto([128, 4], sk.F32)] * 3, {"fusion": sk.FUSE_OFF}).describe()
+    assert [k["name"] for k in d["kernels"]] == ["nbody_force", "nbody_kick_drift"]
+    with pytest.raises(sk.SkelError) as e:
+        sk.Plan(sk.Pipeline(sk.Map("leapfrog", dt=1e-3), sk.Map("nbody_force", eps=0.01, G=1.0)),
+                [sk.proto([8, 4], sk.F32)] * 3)
+    assert e.value.status == sk.ETYPE
+
+
+def test_vector_chain_grouping():
+    st = [("saxpy", {"a": 1.5}), ("mirror", {}), ("saxpy", {"a": -2.0})]
+    root = sk.image_chain(st, "sum")
+    args = [sk.proto([1000], sk.F32)] * 4 + [sk.proto([1], sk.F32)]
+    d = sk.Plan(root, args).describe()
+    assert d["domain"] == "f32" and len(d["kernels"]) == 1
+    d = sk.Plan(root, args, {"fusion": sk.FUSE_OFF}).describe()
+    assert len(d["kernels"]) == 4 and d["kernels"][-1]["reduce"]
+
+
+def test_mirror_only_chain_takes_domain_from_arguments():
+    d = sk.Plan(sk.Map("mirror"), [sk.proto([9], sk.F32)] * 2).describe()
+    assert d["domain"] == "f32"
+    d = sk.Plan(sk.Map("mirror"), img(3, 3)).describe()
+    assert d["domain"] == "u8"
+
+
+def test_features_reflect_configuration():
+    root = sk.image_chain(CFG2, "hist_sum")
+    f_on = sk.features(root, hist_args(1024, 1024))
+    f_off = sk.features(root, hist_args(1024, 1024), {"fusion": sk.FUSE_OFF})
+    assert f_on.shape == (24,)
+    assert list(f_on[:6]) == [1, 1, 1, 1, 0, 1]
+    assert f_on[6] == 4 and f_on[7] == 20 and f_on[8] == 1
+    assert f_on[10] == 1 and f_off[10] == 5                 # kernels
+    assert f_off[11:15].tolist() == [1, 1, 1, 0]            # stage boundaries after stages 0..2
+    assert f_on[21] == 1 and f_off[21] == 0                 # reduce fused
+    assert f_off[22] > f_on[22]                             # more algorithmic bytes unfused
+
+
+def test_kernel_constants_exact():
+    # constants the image kernels use in place of divisions
+    assert all(b - 33 * ((b * 249) >> 13) == b % 33 for b in range(256))
+    assert all((s * 5243) >> 17 == s // 25 for s in range(25 * 255 + 1))
+    assert all(b * 249 < 65536 for b in range(256))

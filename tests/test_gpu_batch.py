@@ -1,0 +1,99 @@
+"""GPU parity of batched execution (many uneven requests in one persistent,
+graph-replayed launch): every request equals the oracle's single-request
+result, byte for byte, with its own histogram and sums."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import paper_1510_06585_amd as sk
+import synth
+from gpu_helpers import assert_image_equal, cuda
+
+pytestmark = pytest.mark.gpu
+
+CFG2 = [("noise", {"seed": synth.NOISE_SEED}), ("solarise", {}), ("blur5", {}), ("mirror", {})]
+
+
+def make_reqs(sides, seed0, reduce="hist_sum"):
+    reqs, imgs = [], []
+    for r, (H, W) in enumerate(sides):
+        img = synth.image(seed0 + r, H, W)
+        x = cuda(img)
+        a = [x, torch.empty_like(x)]
+        if reduce == "hist_sum":
+            a += [torch.full((4, 256), 5, dtype=torch.int32, device="cuda"),
+                  torch.full((4,), 5, dtype=torch.int64, device="cuda")]
+        reqs.append(a)
+        imgs.append(img)
+    return reqs, imgs
+
+
+def plan_for(stages, reduce="hist_sum", options=None):
+    proto = [sk.proto([8, 8, 4], sk.U8)] * 2
+    if reduce == "hist_sum":
+        proto += [sk.proto([4, 256], sk.U32), sk.proto([4], sk.U64)]
+    return sk.Plan(sk.image_chain(stages, reduce), proto, options)
+
+
+def test_small_uneven_batch_against_oracle():
+    rng = np.random.default_rng(21)
+    sides = [(int(rng.integers(1, 300)), int(rng.integers(1, 700))) for _ in range(40)] + [(0, 5), (3, 0)]
+    reqs, imgs = make_reqs(sides, 1000)
+    for opt in ({"tile_h": 16}, {"tile_h": 5, "wg": 64}):
+        p = plan_for(CFG2, options=opt)
+        for rep in range(2):   # capture, then replay of the same request set
+            p.batch_run(reqs)
+            torch.cuda.synchronize()
+            for (H, W), img, a in zip(sides, imgs, reqs):
+                ref, rh, rs = oracle.run_image_pipeline(img, CFG2, "hist_sum")
+                assert_image_equal(a[1].cpu().numpy(), ref, f"{H}x{W} {opt} rep{rep}")
+                assert (a[2].cpu().numpy().view(np.uint32) == rh).all()
+                assert (a[3].cpu().numpy().view(np.uint64) == rs).all()
+
+
+def test_pointwise_batch_without_reduce():
+    st = [("noise", {"seed": 4}), ("mirror", {}), ("solarise", {})]
+    sides = [(5, 9), (300, 257), (1, 1), (64, 1000)]
+    reqs, imgs = make_reqs(sides, 50, reduce=None)
+    p = plan_for(st, reduce=None)
+    p.batch_run(reqs)
+    torch.cuda.synchronize()
+    for img, a in zip(imgs, reqs):
+        assert_image_equal(a[1].cpu().numpy(), oracle.run_image_pipeline(img, st), "pointwise batch")
+
+
+def test_config4_256_requests_match_single_runs_and_oracle_sample():
+    sides = synth.batch_sides(synth.SEED_BATCH, 256)
+    reqs, imgs = make_reqs([(s, s) for s in sides], 4000)
+    p = plan_for(CFG2, options={"tile_h": 64})
+    p.batch_run(reqs)
+    torch.cuda.synchronize()
+    order = np.argsort(sides)
+    sample = set([int(order[0]), int(order[-1]), int(order[128])] + [int(i) for i in np.arange(0, 256, 51)])
+    for r in range(256):
+        s = sides[r]
+        a = reqs[r]
+        h = a[2].cpu().numpy().view(np.uint32)
+        sm = a[3].cpu().numpy().view(np.uint64)
+        assert int(h.sum()) == 4 * s * s and (h[:, 128:] == 0).all()
+        assert all(int(sm[c]) == int((np.arange(256) * h[c].astype(np.int64)).sum()) for c in range(4))
+        if r in sample:
+            ref, rh, rs = oracle.run_image_pipeline(imgs[r], CFG2, "hist_sum")
+            assert_image_equal(a[1].cpu().numpy(), ref, f"request {r} side {s}")
+            assert (h == rh).all() and (sm == rs).all()
+        else:
+            single = [a[0], torch.empty_like(a[0]), torch.empty_like(a[2]), torch.empty_like(a[3])]
+            q = sk.Plan(sk.image_chain(CFG2, "hist_sum"), single)
+            q.run(single)
+            torch.cuda.synchronize()
+            assert torch.equal(single[1], a[1]) and torch.equal(single[2], a[2]) and torch.equal(single[3], a[3])
+            q.destroy()
+
+
+def test_batch_needs_a_fused_plan():
+    p = plan_for(CFG2, options={"fusion": sk.FUSE_OFF})
+    reqs, _ = make_reqs([(4, 4)], 1)
+    with pytest.raises(sk.SkelError) as e:
+        p.batch_run(reqs)
+    assert e.value.status == sk.EUNSUPPORTED

@@ -1,0 +1,144 @@
+"""GPU cost-model MLP kernels against the fp64 oracle: forward pass, loss and
+gradient of one batch, the Adam update, a short training trajectory; and the
+training / selection entry points on a synthetic tuning database."""
+import os
+
+import numpy as np
+import pytest
+import torch
+
+import paper_1510_06585_amd as sk
+import synth
+from oracle import mlp
+
+pytestmark = pytest.mark.gpu
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).cuda()
+
+
+def relerr(a, b):
+    return float(np.linalg.norm(np.asarray(a, np.float64) - b) / max(np.linalg.norm(b), 1e-30))
+
+
+def batch(seed, n):
+    rng = np.random.default_rng(seed)
+    X = rng.normal(size=(n, 24)).astype(np.float32)
+    t = rng.normal(size=n).astype(np.float32)
+    theta = synth.mlp_init(seed).astype(np.float32)
+    theta[1536:1600] = rng.uniform(-0.2, 0.2, 64).astype(np.float32)
+    theta[5696:5760] = rng.uniform(-0.2, 0.2, 64).astype(np.float32)
+    return X, t, theta
+
+
+@pytest.mark.parametrize("n", [1, 7, 256, 1000])
+def test_forward_matches_oracle(n):
+    X, t, theta = batch(n, n)
+    y = torch.empty(n, dtype=torch.float32, device="cuda")
+    sk.mlp_forward(dev(theta), dev(X), y)
+    torch.cuda.synchronize()
+    ref, _ = mlp.forward(theta.astype(np.float64), X.astype(np.float64))
+    assert relerr(y.cpu().numpy(), ref) <= 1e-5
+
+
+@pytest.mark.parametrize("n", [1, 33, 256])
+def test_gradient_matches_oracle(n):
+    X, t, theta = batch(100 + n, n)
+    g = torch.empty(5825, dtype=torch.float32, device="cuda")
+    L = torch.empty(1, dtype=torch.float32, device="cuda")
+    sk.mlp_grad(dev(theta), dev(X), dev(t), g, L)
+    torch.cuda.synchronize()
+    Lr, gr = mlp.loss_and_grad(theta.astype(np.float64), X.astype(np.float64), t.astype(np.float64))
+    assert abs(float(L.cpu()[0]) - Lr) <= 1e-5 * abs(Lr)
+    gg = g.cpu().numpy()
+    for lo, hi in ((0, 1536), (1536, 1600), (1600, 5696), (5696, 5760), (5760, 5824), (5824, 5825)):
+        assert relerr(gg[lo:hi], gr[lo:hi]) <= 1e-4, (lo, hi)
+
+
+def test_adam_matches_oracle_and_training_trajectory():
+    X, t, theta = batch(7, 512)
+    P = dev(theta)
+    m = torch.zeros(5825, device="cuda")
+    v = torch.zeros(5825, device="cuda")
+    g = torch.empty(5825, device="cuda")
+    L = torch.empty(1, device="cuda")
+    th = theta.astype(np.float64)
+    mo = np.zeros(5825)
+    vo = np.zeros(5825)
+    losses = []
+    for step in range(1, 41):
+        sl = slice(((step - 1) % 4) * 128, ((step - 1) % 4) * 128 + 128)
+        sk.mlp_grad(P, dev(X[sl]), dev(t[sl]), g, L)
+        sk.mlp_adam(P, g, m, v, step)
+        Lr, gr = mlp.loss_and_grad(th, X[sl].astype(np.float64), t[sl].astype(np.float64))
+        th, mo, vo = mlp.adam_step(th, gr, mo, vo, step)
+        torch.cuda.synchronize()
+        losses.append((float(L.cpu()[0]), Lr))
+    # same trajectory within fp32 rounding
+    assert relerr(P.cpu().numpy(), th) <= 1e-4
+    assert losses[-1][1] < losses[0][1]
+    assert abs(losses[-1][0] - losses[-1][1]) <= 1e-3 * losses[-1][1]
+
+
+def _masks(comp):
+    """Every valid fusion partition of a composition (split bits after each stage
+    and, with a reduce, one bit for a separate reduce kernel)."""
+    k = len(comp["stages"])
+    nbits = k - 1 + (1 if comp["reduce"] else 0)
+    out = []
+    for m in range(1 << nbits):
+        nblur, ok = 0, True
+        for i, (n, _) in enumerate(comp["stages"]):
+            nblur += n == "blur5"
+            ok &= nblur <= 1
+            if i < k - 1 and (m >> i) & 1:
+                nblur = 0
+        if ok:
+            out.append(m)
+    return out
+
+
+def _synthetic_db(path, rng):
+    """Rows shaped like the tuner's, with runtimes from a known law
+    t = bytes / BW + launches * 4 us (+3 us for 64-thread work-groups), over the
+    same configuration space the selector scores."""
+    rows = 0
+    with open(path, "w") as f:
+        for c in range(60):
+            comp = synth.composition(rng, log2_lo=12, log2_hi=22)
+            if comp["domain"] != "u8":
+                continue
+            root = sk.image_chain(comp["stages"], comp["reduce"])
+            proto = [sk.proto([comp["H"], comp["W"], 4], sk.U8)] * 2
+            if comp["reduce"] == "hist_sum":
+                proto += [sk.proto([4, 256], sk.U32), sk.proto([4], sk.U64)]
+            elif comp["reduce"] == "sum":
+                proto += [sk.proto([4], sk.U64)]
+            for m in _masks(comp):
+                for wg in (64, 256):
+                    o = {"fusion": sk.FUSE_MASK, "split_mask": m, "wg": wg}
+                    feat = sk.features(root, proto, o)
+                    t_us = 2.0 ** feat[22] / 5e6 + 4.0 * 2.0 ** feat[23] + (3.0 if wg == 64 else 0.0)
+                    f.write(f"c{c},{sk.FUSE_MASK},{m},0,{wg},1,0," + ",".join(f"{x:.6g}" for x in feat)
+                            + f",{t_us:.4f},{t_us:.4f}\n")
+                    rows += 1
+    return rows
+
+
+def test_cost_train_and_select_on_synthetic_law(tmp_path):
+    rng = np.random.default_rng(11)
+    db = str(tmp_path / "db.csv")
+    assert _synthetic_db(db, rng) > 100
+    w0 = str(tmp_path / "w0.txt")
+    w = str(tmp_path / "w.txt")
+    l0 = sk.cost_train(db, w0, 0, seed=3)
+    l1 = sk.cost_train(db, w, 300, seed=3)
+    assert l1 < 0.1 * l0
+    # the trained model prefers the fused plan of an unseen chain
+    comp_root = sk.image_chain([("noise", {"seed": 1}), ("solarise", {}), ("mirror", {})], "hist_sum")
+    proto = [sk.proto([1024, 1024, 4], sk.U8)] * 2 + [sk.proto([4, 256], sk.U32), sk.proto([4], sk.U64)]
+    o = sk.cost_select(comp_root, proto, w)
+    d = sk.Plan(comp_root, proto, o).describe()
+    assert len(d["kernels"]) == 1
+    assert os.path.getsize(w) > 1000
