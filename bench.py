@@ -1,0 +1,310 @@
+"""Benchmark of the skeleton hot path on one MI355X.
+
+Headline workload: the fused Pipeline + MapReduce over an 8192 x 8192 RGBA
+uint8 image (noise -> solarise -> 5x5 blur -> mirror, then a per-channel
+256-bin histogram and uint64 channel sums), one plan run per step, inputs
+resident in HBM.  Prints ONE JSON line with throughput (Gelem/s = Gpixel/s),
+the roofline of the dominant kernel measured live with HIP events, the CPU
+oracle's throughput on the host, the fused-vs-plain speedup and, under
+"extras", the other skeletons (plain filter pipeline, N-body Loop, batched
+requests).
+
+  python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-extras]
+                  [--no-cpu-baseline] [--selector]
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0                                   # MI355X HBM3E, GB/s
+VALU_LANE_OPS = 256 * 64 * 2.4e9                        # 256 CUs x 64 lanes x 2.4 GHz
+NBODY_LANE_OPS_PER_PAIR = 16                            # 12 VALU + v_rsq_f32 (quarter rate)
+METRIC = "Gelem/s & % HBM roofline per skeleton; fused/learned vs plain speedup"
+CFG2 = [("noise", {"seed": 0x1510}), ("solarise", {}), ("blur5", {}), ("mirror", {})]
+CFG1 = [("noise", {"seed": 0x1510}), ("solarise", {}), ("mirror", {})]
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def timed_runs(fn, steps, warmup):
+    """Runs fn() warmup times untimed, then `steps` times bracketed by device
+    synchronisation; returns (wall seconds, event milliseconds)."""
+    import torch
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    e0.record()
+    for _ in range(steps):
+        fn()
+    e1.record()
+    torch.cuda.synchronize()
+    return time.perf_counter() - t0, e0.elapsed_time(e1)
+
+
+def kernel_ms(plan, bound, kernel, steps):
+    """Average duration of one kernel of a plan, from HIP events the plan
+    records around that kernel on the launch stream."""
+    import torch
+    starts = [torch.cuda.Event(enable_timing=True) for _ in range(steps)]
+    ends = [torch.cuda.Event(enable_timing=True) for _ in range(steps)]
+    for i in range(steps):
+        plan.kernel_events(kernel, starts[i], ends[i])
+        plan.run(bound)
+    torch.cuda.synchronize()
+    plan.kernel_events(-1)
+    return sum(s.elapsed_time(e) for s, e in zip(starts, ends)) / steps
+
+
+def traffic_for(kernel: str, algo_bytes: float):
+    """HBM bytes per launch from the committed rocprofv3 counter summary of this
+    kernel, or None when there is none or the kernel source changed since."""
+    path = os.path.join(ROOT, "profiles", f"traffic_{kernel}.json")
+    if not os.path.exists(path):
+        return None
+    rec = json.load(open(path))
+    src = os.path.join(ROOT, "paper_1510_06585_amd", "csrc", rec["source"])
+    if not os.path.exists(src) or hashlib.sha256(open(src, "rb").read()).hexdigest() != rec["source_sha256"]:
+        return None
+    return rec["bytes_per_launch"]
+
+
+def cpu_baseline(img, budget_s=12.0):
+    """The oracle as it stands on the host's cores: the full chain over the
+    full 8192 x 8192 image, every stage materialised, repeated for ~budget_s."""
+    import oracle
+    oracle.lib()
+    reps, t = 0, 0.0
+    while reps < 2 or (t < budget_s and reps < 8):
+        t0 = time.perf_counter()
+        oracle.run_image_pipeline(img, CFG2, "hist_sum")
+        t += time.perf_counter() - t0
+        reps += 1
+    px = img.shape[0] * img.shape[1]
+    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    return {"value": round(px * reps / t / 1e9, 6), "unit": "Gelem/s", "cores": cores, "kind": "oracle",
+            "sample": f"full 8192x8192 image x {reps} runs (noise, solarise, blur5, mirror each materialised, "
+                      f"then histogram + sums); OpenMP over rows in noise/blur, other stages single-threaded",
+            "seconds": round(t, 3)}
+
+
+def image_args(img, reduce="hist_sum"):
+    import torch
+    x = torch.from_numpy(img).cuda()
+    a = [x, torch.empty_like(x)]
+    if reduce == "hist_sum":
+        a += [torch.zeros(4, 256, dtype=torch.int32, device="cuda"), torch.zeros(4, dtype=torch.int64, device="cuda")]
+    return a
+
+
+def bench_config2(steps, warmup, do_cpu):
+    import torch
+    import paper_1510_06585_amd as sk
+    import synth
+    H = W = 8192
+    img = synth.image(synth.SEED_PIPE_FUSED, H, W)
+    args = image_args(img)
+    bound = sk.bind(args)
+    root = sk.image_chain(CFG2, "hist_sum")
+    fused = sk.Plan(root, args)
+    plain = sk.Plan(root, args, {"fusion": sk.FUSE_OFF})
+    wall, ev_ms = timed_runs(lambda: fused.run(bound), steps, warmup)
+    ms_step = wall * 1e3 / steps
+    k_ms = kernel_ms(fused, bound, 0, steps)
+    _, plain_ms = timed_runs(lambda: plain.run(bound), max(5, steps // 4), 3)
+    plain_ms /= max(5, steps // 4)
+    desc = fused.describe()
+    algo = 2.0 * H * W * 4 + 4 * 256 * 4 + 4 * 8      # read + write image, hist + sums
+    achieved = algo / (k_ms * 1e-3) / 1e9
+    kname = desc["kernels"][0]["name"]
+    traffic = traffic_for(kname, algo)
+    out = {
+        "metric": METRIC,
+        "value": round(H * W * steps / wall / 1e9, 4),
+        "unit": "Gelem/s",
+        "n_gpus": 1,
+        "steps": steps,
+        "warmup": warmup,
+        "ms_per_step": round(ms_step, 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u8",
+        "data": "synthetic",
+        "config": {"workload": "fused Pipeline+MapReduce, 8192x8192 RGBA u8: noise>solarise>blur5x5>mirror, "
+                               "256-bin per-channel histogram + u64 channel sums",
+                   "H": H, "W": W, "kernels": len(desc["kernels"]), "tile_h": desc["config"]["tile_h"],
+                   "wg": desc["config"]["wg"]},
+        "roofline": {"bound": "hbm", "kernel": kname, "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": traffic, "kernel_ms": round(k_ms, 5), "algorithmic_bytes": int(algo)},
+        "event_ms_per_step": round(ev_ms / steps, 5),
+        "plain_ms_per_step": round(plain_ms, 5),
+        "fused_vs_plain_speedup": round(plain_ms / (ev_ms / steps), 3),
+    }
+    fused.destroy()
+    plain.destroy()
+    del args, bound
+    torch.cuda.empty_cache()
+    return out, img
+
+
+def bench_config1():
+    import paper_1510_06585_amd as sk
+    import synth
+    img = synth.image(synth.SEED_PIPE_PLAIN, 1024, 1024)
+    args = image_args(img, None)
+    b = sk.bind(args)
+    root = sk.image_chain(CFG1)
+    res = {}
+    for name, opt in (("plain", {"fusion": sk.FUSE_OFF}), ("fused", {})):
+        p = sk.Plan(root, args, opt)
+        _, ms = timed_runs(lambda: p.run(b), 200, 20)
+        res[f"{name}_ms"] = round(ms / 200, 5)
+        res[f"{name}_gelem_s"] = round(1024 * 1024 / (ms / 200 * 1e-3) / 1e9, 3)
+        p.destroy()
+    res["fused_vs_plain_speedup"] = round(res["plain_ms"] / res["fused_ms"], 3)
+    return res
+
+
+def bench_nbody():
+    import torch
+    import paper_1510_06585_amd as sk
+    import synth
+    N, iters = 65536, 20
+    pos, vel = synth.nbody(synth.SEED_NBODY, N)
+    args = [torch.from_numpy(pos).cuda(), torch.from_numpy(vel).cuda(), torch.empty(N, 4, device="cuda")]
+    b = sk.bind(args)
+    res = {}
+    for name, opt in (("graph_fused", {}), ("eager_unfused", {"fusion": sk.FUSE_OFF, "variant": 1})):
+        p = sk.Plan(sk.nbody_loop(iters), args, opt)
+        _, ms = timed_runs(lambda: p.run(b), 3, 1)
+        ms /= 3
+        pairs = float(N) * N * iters
+        res[f"{name}_ms_per_loop"] = round(ms, 4)
+        res[f"{name}_ginteractions_s"] = round(pairs / (ms * 1e-3) / 1e9, 2)
+        p.destroy()
+    rate = float(N) * N * iters / (res["graph_fused_ms_per_loop"] * 1e-3)
+    peak = VALU_LANE_OPS / NBODY_LANE_OPS_PER_PAIR
+    res["roofline"] = {"bound": "alu", "achieved": round(rate / 1e9, 2), "peak": round(peak / 1e9, 2),
+                       "unit": "Ginteractions/s", "frac": round(rate / peak, 4),
+                       "note": "peak = 256 CUs x 64 lanes x 2.4 GHz / 16 lane-cycles per pair"}
+    res["tflops_20flop_convention"] = round(rate * 20 / 1e12, 2)
+    return res
+
+
+def bench_batch():
+    import torch
+    import paper_1510_06585_amd as sk
+    import synth
+    sides = synth.batch_sides(synth.SEED_BATCH, 256)
+    reqs = []
+    for r, s in enumerate(sides):
+        reqs.append(image_args(synth.image(4000 + r, s, s)))
+    px = sum(s * s for s in sides)
+    algo = sum(2.0 * s * s * 4 + 4128 for s in sides)
+    root = sk.image_chain(CFG2, "hist_sum")
+    proto = [sk.proto([8, 8, 4], sk.U8)] * 2 + [sk.proto([4, 256], sk.U32), sk.proto([4], sk.U64)]
+    res = {"requests": 256, "pixels": px}
+    bp = sk.Plan(root, proto, {"tile_h": 64})
+    _, ms = timed_runs(lambda: bp.batch_run(reqs), 10, 2)
+    ms /= 10
+    res["batched_ms"] = round(ms, 4)
+    res["batched_gelem_s"] = round(px / (ms * 1e-3) / 1e9, 3)
+    res["batched_hbm_frac"] = round(algo / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)
+    for name, opt in (("sequential_fused", {}), ("sequential_plain", {"fusion": sk.FUSE_OFF})):
+        plans = [(sk.Plan(root, a, opt), sk.bind(a)) for a in reqs]
+
+        def run_all():
+            for p, b in plans:
+                p.run(b)
+        _, ms2 = timed_runs(run_all, 3, 1)
+        ms2 /= 3
+        res[f"{name}_ms"] = round(ms2, 4)
+        res[f"batched_vs_{name}_speedup"] = round(ms2 / ms, 3)
+        for p, _ in plans:
+            p.destroy()
+    bp.destroy()
+    del reqs
+    torch.cuda.empty_cache()
+    return res
+
+
+def profile_run(steps):
+    """Short run for hardware-counter passes: the fused config-2 kernel and a
+    plain copy of the same image (the byte-count reference), `steps` each."""
+    import torch
+    import paper_1510_06585_amd as sk
+    import synth
+    img = synth.image(synth.SEED_PIPE_FUSED, 8192, 8192)
+    args = image_args(img)
+    fused = sk.Plan(sk.image_chain(CFG2, "hist_sum"), args)
+    copy = sk.Plan(sk.Loop(sk.Map("mirror"), 2), args[:2])   # two mirrors = identity: one copy kernel
+    for _ in range(steps):
+        fused.run(args)
+    for _ in range(steps):
+        copy.run(args[:2])
+    torch.cuda.synchronize()
+    print(json.dumps({"fused": fused.describe()["kernels"][0]["name"], "copy": copy.describe()["kernels"][0]["name"],
+                      "copy_bytes_per_launch": 2 * 8192 * 8192 * 4}), flush=True)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--no-extras", action="store_true")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--selector", action="store_true", help="run the learned-selector experiment instead")
+    ap.add_argument("--profile-run", action="store_true", help="short run for rocprofv3 counter passes")
+    a = ap.parse_args()
+    if a.gpus != 1:
+        print(f"bench.py measures one GPU only (asked for --gpus {a.gpus}); multi-GPU runs are not part "
+              f"of this build", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    import paper_1510_06585_amd as sk
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(1)
+    torch.cuda.set_device(0)
+    sk.lib()
+    if a.profile_run:
+        profile_run(a.steps)
+        return
+    if a.selector:
+        from paper_1510_06585_amd import selector
+        print(json.dumps(selector.experiment()), flush=True)
+        return
+    log("config 2: fused pipeline + mapreduce 8192x8192")
+    out, img = bench_config2(a.steps, a.warmup, not a.no_cpu_baseline)
+    if not a.no_extras:
+        extras = {}
+        log("config 1: filter pipeline 1024x1024 plain vs fused")
+        extras["filter_pipeline_1024"] = bench_config1()
+        log("config 3: n-body 65536 x 20 iterations")
+        extras["nbody_65536_x20"] = bench_nbody()
+        log("config 4: 256 batched uneven requests")
+        extras["batched_256"] = bench_batch()
+        out["extras"] = extras
+    if not a.no_cpu_baseline:
+        log("cpu baseline: oracle on the host")
+        out["cpu_baseline"] = cpu_baseline(img)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -242,6 +242,15 @@ skel_status skel_batch_run(skel_plan plan, const skel_buffer* args, int32_t narg
  * stages, configuration) into buf (NUL-terminated, truncated to len). */
 skel_status skel_plan_describe(skel_plan plan, char* buf, size_t len);
 
+/* Measurement hook: while set, every run of the plan records hipEvent_t
+ * `start` on its stream immediately before launching kernel `kernel` (an
+ * index into the kernels skel_plan_describe lists) and `end` immediately
+ * after it, so the kernel's own duration can be read with
+ * hipEventElapsedTime.  kernel < 0 or NULL events clear the hook.  Not
+ * applied inside captured graphs (N-body loops, batched runs).  The caller
+ * owns the events. */
+skel_status skel_plan_kernel_events(skel_plan plan, int32_t kernel, void* start, void* end);
+
 /* Frees the plan and everything it owns; waits for none of its work (the
  * caller synchronises first).  NULL is a no-op. */
 skel_status skel_plan_destroy(skel_plan plan);
@@ -253,16 +262,25 @@ skel_status skel_sync(void* stream);
 const char* skel_last_error(void);
 
 /* ------------------------------------------- auto-tuning and cost model */
-/* Auto Tuner (Sec. 2.2; search in the spirit of Algorithm 1): times every
- * valid configuration of `root` over the given (device) arguments -- fusion
+/* Auto Tuner (Sec. 2.2; search in the spirit of Algorithm 1): times the
+ * valid configurations of `root` over the given (device) arguments -- fusion
  * partition x work-group size x vectors per thread x tile height, filtered
- * by the partitioning constraints of Sec. 3.1 and an occupancy threshold --
- * with 3 warm-up runs and the median of `reps` timed runs each (reps <= 0:
- * 10).  Appends one row per configuration to the text database `db_path`
- * (may be NULL) and writes the fastest configuration to *best and its median
- * time in microseconds to *best_us (may be NULL).  Synchronises the device. */
+ * by the partitioning constraints of Sec. 3.1 -- with 3 warm-up runs and the
+ * median of `reps` timed runs each (reps <= 0: 10).  max_configs <= 0 times
+ * every configuration (exhaustive); otherwise a sample of that many, drawn
+ * with `sample_seed`, always including the default configuration.  Appends
+ * one row per timed configuration to the text database `db_path` (may be
+ * NULL): key, fusion, split_mask, tile_h, wg, ept, variant, the 24 cost-model
+ * features, median and minimum microseconds.  Writes the fastest
+ * configuration to *best and its median time to *best_us (may be NULL).
+ * Synchronises the device; the arguments' contents are overwritten. */
 skel_status skel_tune(skel_node root, const skel_buffer* args, int32_t nargs, const char* db_path,
-                      int32_t reps, skel_plan_opts* best, double* best_us);
+                      int32_t reps, int32_t max_configs, uint64_t sample_seed, skel_plan_opts* best,
+                      double* best_us);
+
+/* Number of valid configurations skel_tune would time exhaustively for
+ * (root, shapes), i.e. the cost model's candidate set. */
+skel_status skel_config_count(skel_node root, const skel_buffer* proto, int32_t nargs, int32_t* count);
 
 /* Number of features of the cost model (24) and the feature vector of
  * (root, shapes, opts).  feat must hold skel_feature_count() floats. */

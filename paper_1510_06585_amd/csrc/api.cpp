@@ -133,7 +133,8 @@ skel_status run_image(skel_plan p, const skel_buffer* args, hipStream_t s) {
     } else if (L.red == SKEL_RED_SUM) {
         HIP_TRY(launch_fill_u32(args[2].data, 8, 0, s));
     }
-    for (Kernel& k : p->kernels) {
+    for (size_t ki = 0; ki < p->kernels.size(); ++ki) {
+        Kernel& k = p->kernels[ki];
         ImgGroupArgs A = k.img;
         A.in = (const uint8_t*)resolve_img(p, args, k.src);
         A.out = (uint8_t*)resolve_img(p, args, k.dst);
@@ -141,7 +142,10 @@ skel_status run_image(skel_plan p, const skel_buffer* args, hipStream_t s) {
             A.hist = L.red == SKEL_RED_HIST256_SUM ? (uint32_t*)args[2].data : nullptr;
             A.sum = L.red == SKEL_RED_HIST256_SUM ? (uint64_t*)args[3].data : (uint64_t*)args[2].data;
         }
+        const bool prof = (int)ki == p->prof_kernel;
+        if (prof) HIP_TRY(hipEventRecord(p->prof_start, s));
         HIP_TRY(launch_img_group(A, k.blur, k.reduce, k.wg, p->cfg.variant, s, &k.name));
+        if (prof) HIP_TRY(hipEventRecord(p->prof_end, s));
     }
     return SKEL_OK;
 }
@@ -152,7 +156,8 @@ skel_status run_vector(skel_plan p, const skel_buffer* args, hipStream_t s) {
     const int out = nargs - 1 - (L.red >= 0 ? 1 : 0);
     float* sum_out = L.red >= 0 ? (float*)args[nargs - 1].data : nullptr;
     if (L.red >= 0 && p->sh.n == 0) HIP_TRY(launch_fill_u32(sum_out, 1, 0, s));
-    for (Kernel& k : p->kernels) {
+    for (size_t ki = 0; ki < p->kernels.size(); ++ki) {
+        Kernel& k = p->kernels[ki];
         VecGroupArgs A = k.vec;
         auto res = [&](int id) -> float* {
             if (id == -1) return (float*)args[0].data;
@@ -168,7 +173,10 @@ skel_status run_vector(skel_plan p, const skel_buffer* args, hipStream_t s) {
             A.ticket = p->ticket;
             A.sum_out = sum_out;
         }
+        const bool prof = (int)ki == p->prof_kernel;
+        if (prof) HIP_TRY(hipEventRecord(p->prof_start, s));
         HIP_TRY(launch_vec_group(A, k.grid, k.wg, s, &k.name));
+        if (prof) HIP_TRY(hipEventRecord(p->prof_end, s));
     }
     return SKEL_OK;
 }
@@ -423,6 +431,21 @@ skel_status skel_plan_describe(skel_plan p, char* buf, size_t len) {
     s += tmp;
     strncpy(buf, s.c_str(), len - 1);
     buf[len - 1] = 0;
+    return SKEL_OK;
+}
+
+skel_status skel_plan_kernel_events(skel_plan p, int32_t kernel, void* start, void* end) {
+    clear_error();
+    if (!p) return set_error(SKEL_EINVAL, "null plan");
+    if (kernel >= (int32_t)p->kernels.size()) return set_error(SKEL_EINVAL, "plan has %d kernels", (int)p->kernels.size());
+    if (kernel < 0 || !start || !end) {
+        p->prof_kernel = -1;
+        p->prof_start = p->prof_end = nullptr;
+        return SKEL_OK;
+    }
+    p->prof_kernel = kernel;
+    p->prof_start = (hipEvent_t)start;
+    p->prof_end = (hipEvent_t)end;
     return SKEL_OK;
 }
 

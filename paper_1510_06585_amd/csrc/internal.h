@@ -128,6 +128,9 @@ struct skel_plan_s {
     hipGraphExec_t bexec = nullptr;
     std::vector<int64_t> bkey;
     int batch_grid = 0;
+    // measurement hook (skel_plan_kernel_events)
+    int prof_kernel = -1;
+    hipEvent_t prof_start = nullptr, prof_end = nullptr;
 };
 
 skel_status skel_ensure_resources(skel_plan p);

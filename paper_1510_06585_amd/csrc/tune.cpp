@@ -14,6 +14,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <random>
 
 #include "internal.h"
 #include "tune.h"
@@ -82,7 +83,6 @@ static double lg2(double v) { return v > 0 ? std::log2(v) : 0.0; }
 void features(const Linear& L, const Shape& sh, const Config& c, float* f) {
     for (int i = 0; i < kNumFeatures; ++i) f[i] = 0.0f;
     std::vector<Kernel> ks;
-    std::string dummy;
     build_kernels(L, sh, c, ks);
     int cnt[6] = {0, 0, 0, 0, 0, 0};
     for (const Stage& s : L.st) {
@@ -185,8 +185,22 @@ extern "C" skel_status skel_features(skel_node root, const skel_buffer* proto, i
     return SKEL_OK;
 }
 
+extern "C" skel_status skel_config_count(skel_node root, const skel_buffer* proto, int32_t nargs, int32_t* count) {
+    clear_error();
+    if (!root || !count) return set_error(SKEL_EINVAL, "null root or result");
+    Linear L;
+    Shape sh;
+    skel_status st = linearize(root, L);
+    if (!st && L.dom == DOM_NONE) L.dom = (nargs > 0 && proto[0].dtype == SKEL_U8) ? DOM_U8 : DOM_F32;
+    if (!st) st = derive_shape(L, proto, nargs, sh);
+    if (st) return st;
+    *count = (int32_t)enumerate_configs(L, sh).size();
+    return SKEL_OK;
+}
+
 extern "C" skel_status skel_tune(skel_node root, const skel_buffer* args, int32_t nargs, const char* db_path,
-                                 int32_t reps, skel_plan_opts* best, double* best_us) {
+                                 int32_t reps, int32_t max_configs, uint64_t sample_seed, skel_plan_opts* best,
+                                 double* best_us) {
     clear_error();
     if (!root || !best) return set_error(SKEL_EINVAL, "null root or result");
     Linear L;
@@ -198,6 +212,17 @@ extern "C" skel_status skel_tune(skel_node root, const skel_buffer* args, int32_
     if (reps <= 0) reps = 10;
     std::vector<Config> cands = enumerate_configs(L, sh);
     if (cands.empty()) return set_error(SKEL_EUNSUPPORTED, "no valid configuration");
+    if (max_configs > 0 && (int)cands.size() > max_configs) {
+        // Sample without replacement; the default configuration stays first.
+        Config def;
+        skel_plan_opts d;
+        skel_plan_opts_default(&d);
+        resolve_config(L, sh, &d, def);
+        std::mt19937_64 g(sample_seed);
+        std::shuffle(cands.begin(), cands.end(), g);
+        cands.resize(max_configs - 1);
+        cands.insert(cands.begin(), def);
+    }
     FILE* db = nullptr;
     if (db_path && *db_path) {
         db = fopen(db_path, "a");

@@ -1,0 +1,215 @@
+"""Learned configuration selection: the cost-model experiment.
+
+The paper builds a profile per (computation, workload) pair by search
+(Algorithm 1) and derives configurations for new pairs by interpolating over
+stored profiles (Sec. 3.2; Euclidean nearest neighbour above three
+dimensions).  This driver measures how well the GPU-trained MLP picks a fused
+plan and tile configuration for compositions it has never seen:
+
+1. draw random skeleton compositions (2-6 stages over noise, solarise, mirror,
+   5x5 blur / saxpy, mirror, optional sum reduce; 2^16..2^26 elements), split
+   by composition into a training set and a held-out set;
+2. time a sample of configurations of every training composition with the
+   auto-tuner (labels), and every configuration of every held-out composition
+   (exhaustive: its best is the reference);
+3. train the MLP on the GPU (skel_cost_train) and let it pick a configuration
+   for each held-out composition (skel_cost_select);
+4. report the regret t(chosen) / t(best) - 1 next to three baselines: the
+   default plan, nearest-neighbour derivation over the training rows, and the
+   untrained network.
+
+Inputs are seeded random device tensors: runtimes do not depend on values.
+"""
+from __future__ import annotations
+
+import os
+import tempfile
+import time
+
+import numpy as np
+
+from . import skel as sk
+
+_DB_FEAT0 = 7          # first feature column of a tuning-database row
+
+
+def _args_for(comp, gen):
+    import torch
+    if comp["domain"] == "u8":
+        H, W = comp["H"], comp["W"]
+        x = torch.randint(0, 256, (H, W, 4), dtype=torch.uint8, device="cuda", generator=gen)
+        a = [x, torch.empty_like(x)]
+        if comp["reduce"] == "hist_sum":
+            a += [torch.zeros(4, 256, dtype=torch.int32, device="cuda"),
+                  torch.zeros(4, dtype=torch.int64, device="cuda")]
+        elif comp["reduce"] == "sum":
+            a += [torch.zeros(4, dtype=torch.int64, device="cuda")]
+        return a
+    n = comp["n"]
+    x = torch.rand(n, dtype=torch.float32, device="cuda", generator=gen) * 2 - 1
+    a = [x]
+    for name, _ in comp["stages"]:
+        if name == "saxpy":
+            a.append(torch.rand(n, dtype=torch.float32, device="cuda", generator=gen) * 2 - 1)
+    a.append(torch.empty_like(x))
+    if comp["reduce"]:
+        a.append(torch.zeros(1, dtype=torch.float32, device="cuda"))
+    return a
+
+
+def _read_rows(path):
+    rows = []
+    if not os.path.exists(path):
+        return rows
+    for line in open(path):
+        t = line.rstrip("\n").split(",")
+        if len(t) != _DB_FEAT0 + 24 + 2:
+            continue
+        rows.append({"key": t[0], "cfg": tuple(int(v) for v in t[1:7]),
+                     "f": np.array([float(v) for v in t[_DB_FEAT0:_DB_FEAT0 + 24]], np.float64),
+                     "t": float(t[-2])})
+    return rows
+
+
+def _time_default(root, args, reps=10):
+    import torch
+    p = sk.Plan(root, args)
+    b = sk.bind(args)
+    for _ in range(3):
+        p.run(b)
+    torch.cuda.synchronize()
+    ts = []
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        p.run(b)
+        e1.record()
+        e1.synchronize()
+        ts.append(e0.elapsed_time(e1) * 1000.0)
+    p.destroy()
+    return float(np.median(ts))
+
+
+def _match(rows, opts):
+    """Measured time of the row whose configuration equals opts."""
+    key = (opts["fusion"], opts["split_mask"], opts["tile_h"], opts["wg"], opts["ept"], opts["variant"])
+    for r in rows:
+        if r["cfg"] == key:
+            return r["t"]
+    return None
+
+
+def _stats(reg):
+    reg = np.asarray(reg, np.float64)
+    return {"mean": round(float(reg.mean()), 4), "median": round(float(np.median(reg)), 4),
+            "p90": round(float(np.percentile(reg, 90)), 4),
+            "frac_within_10pct": round(float((reg <= 0.10).mean()), 4), "n": int(reg.size)}
+
+
+def experiment(n_train: int = 1000, n_test: int = 200, per_train: int = 20, seed: int = 5,
+               epochs: int = 200, workdir: str | None = None, log=print):
+    import torch
+    import synth
+    rng = np.random.default_rng(seed)
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(seed)
+    workdir = workdir or tempfile.mkdtemp(prefix="skel_selector_")
+    train_db = os.path.join(workdir, "train.csv")
+    test_db = os.path.join(workdir, "test.csv")
+    for p in (train_db, test_db):
+        if os.path.exists(p):
+            os.remove(p)
+    comps, seen = [], set()
+    while len(comps) < n_train + n_test:
+        c = synth.composition(rng)
+        key = (c["domain"], tuple((n, tuple(sorted(p.items()))) for n, p in c["stages"]), c["reduce"], c["n"])
+        if key in seen:
+            continue
+        seen.add(key)
+        comps.append(c)
+    train, test = comps[:n_train], comps[n_train:]
+    t0 = time.time()
+    n_labels = 0
+    for i, c in enumerate(train):
+        root = sk.image_chain(c["stages"], c["reduce"])
+        args = _args_for(c, gen)
+        sk.tune(root, args, train_db, reps=5, max_configs=per_train, sample_seed=seed * 100003 + i)
+        del args
+        if i % 100 == 0:
+            log(f"train {i}/{len(train)} {time.time() - t0:.0f}s")
+    n_labels = len(_read_rows(train_db))
+    t_train_labels = time.time() - t0
+    test_rows, defaults = [], []
+    for i, c in enumerate(test):
+        root = sk.image_chain(c["stages"], c["reduce"])
+        args = _args_for(c, gen)
+        before = len(_read_rows(test_db))
+        sk.tune(root, args, test_db, reps=10)
+        rows = _read_rows(test_db)[before:]
+        test_rows.append(rows)
+        defaults.append(_time_default(root, args))
+        del args
+        if i % 20 == 0:
+            log(f"test {i}/{len(test)} {time.time() - t0:.0f}s")
+    t_labels = time.time() - t0
+    weights = os.path.join(workdir, "cost_model.txt")
+    weights0 = os.path.join(workdir, "cost_model_untrained.txt")
+    init = synth.mlp_init(seed).astype(np.float32)
+    t1 = time.time()
+    loss = sk.cost_train(train_db, weights, epochs, seed=seed, init=init)
+    t_train = time.time() - t1
+    loss0 = sk.cost_train(train_db, weights0, 0, seed=seed, init=init)
+    # nearest-neighbour derivation over the training rows (standardised features)
+    tr = _read_rows(train_db)
+    F = np.stack([r["f"] for r in tr])
+    T = np.log(np.array([r["t"] for r in tr]))
+    mu, sd = F.mean(0), F.std(0)
+    sd[sd < 1e-6] = 1.0
+    Fz = (F - mu) / sd
+    reg = {"model": [], "default": [], "nearest_neighbour": [], "untrained": [], "random": []}
+    for c, rows, tdef in zip(test, test_rows, defaults):
+        root = sk.image_chain(c["stages"], c["reduce"])
+        protos = _args_for_proto(c)
+        best = min(r["t"] for r in rows)
+        for name, w in (("model", weights), ("untrained", weights0)):
+            o = sk.cost_select(root, protos, w)
+            t = _match(rows, o)
+            reg[name].append((t if t is not None else tdef) / best - 1.0)
+        reg["default"].append(tdef / best - 1.0)
+        q = (np.stack([r["f"] for r in rows]) - mu) / sd
+        d2 = ((q[:, None, :] - Fz[None, :, :]) ** 2).sum(-1)
+        pred = T[d2.argmin(1)]
+        reg["nearest_neighbour"].append(rows[int(pred.argmin())]["t"] / best - 1.0)
+        reg["random"].append(rows[int(rng.integers(0, len(rows)))]["t"] / best - 1.0)
+    return {
+        "experiment": "learned config selector",
+        "train_compositions": len(train), "heldout_compositions": len(test), "labels": n_labels,
+        "heldout_configs_timed": int(sum(len(r) for r in test_rows)),
+        "final_train_loss_log_us2": round(float(loss), 5), "untrained_loss": round(float(loss0), 5),
+        "train_seconds_gpu": round(t_train, 2), "label_seconds": round(t_labels, 1),
+        "train_label_seconds": round(t_train_labels, 1),
+        "regret": {k: _stats(v) for k, v in reg.items()},
+        "workdir": workdir,
+    }
+
+
+def _args_for_proto(comp):
+    if comp["domain"] == "u8":
+        H, W = comp["H"], comp["W"]
+        p = [sk.proto([H, W, 4], sk.U8)] * 2
+        if comp["reduce"] == "hist_sum":
+            p += [sk.proto([4, 256], sk.U32), sk.proto([4], sk.U64)]
+        elif comp["reduce"] == "sum":
+            p += [sk.proto([4], sk.U64)]
+        return p
+    n = comp["n"]
+    ns = sum(1 for s, _ in comp["stages"] if s == "saxpy")
+    p = [sk.proto([n], sk.F32)] * (2 + ns)
+    if comp["reduce"]:
+        p.append(sk.proto([1], sk.F32))
+    return p
+
+
+if __name__ == "__main__":
+    import json
+    print(json.dumps(experiment()))

@@ -80,10 +80,14 @@ _SIGS = {
     "skel_batch_run": (ctypes.c_int32, [_vp, ctypes.POINTER(Buffer), ctypes.c_int32, ctypes.c_int32, _vp]),
     "skel_plan_describe": (ctypes.c_int32, [_vp, ctypes.c_char_p, ctypes.c_size_t]),
     "skel_plan_destroy": (ctypes.c_int32, [_vp]),
+    "skel_plan_kernel_events": (ctypes.c_int32, [_vp, ctypes.c_int32, _vp, _vp]),
     "skel_sync": (ctypes.c_int32, [_vp]),
     "skel_last_error": (ctypes.c_char_p, []),
     "skel_tune": (ctypes.c_int32, [_node_p, ctypes.POINTER(Buffer), ctypes.c_int32, ctypes.c_char_p,
-                                   ctypes.c_int32, ctypes.POINTER(PlanOpts), ctypes.POINTER(ctypes.c_double)]),
+                                   ctypes.c_int32, ctypes.c_int32, ctypes.c_uint64, ctypes.POINTER(PlanOpts),
+                                   ctypes.POINTER(ctypes.c_double)]),
+    "skel_config_count": (ctypes.c_int32, [_node_p, ctypes.POINTER(Buffer), ctypes.c_int32,
+                                           ctypes.POINTER(ctypes.c_int32)]),
     "skel_feature_count": (ctypes.c_int32, []),
     "skel_features": (ctypes.c_int32, [_node_p, ctypes.POINTER(Buffer), ctypes.c_int32,
                                        ctypes.POINTER(PlanOpts), ctypes.POINTER(ctypes.c_float)]),
@@ -161,7 +165,22 @@ def proto(shape, dtype: int) -> Buffer:
     return b
 
 
+class Bound:
+    """Pre-marshalled argument list (skips per-call conversion in hot loops).
+    Holds references to the tensors so they outlive the bound arguments."""
+
+    def __init__(self, bufs):
+        self.tensors = list(bufs)
+        self.arr, self.n = _buf_array(self.tensors)
+
+
+def bind(bufs) -> Bound:
+    return Bound(bufs)
+
+
 def _buf_array(bufs):
+    if isinstance(bufs, Bound):
+        return bufs.arr, bufs.n
     arr = (Buffer * max(1, len(bufs)))()
     for i, b in enumerate(bufs):
         arr[i] = b if isinstance(b, Buffer) else buffer(b)
@@ -274,6 +293,13 @@ class Plan:
         _check(lib().skel_plan_describe(self._h, buf, len(buf)))
         return json.loads(buf.value.decode())
 
+    def kernel_events(self, kernel: int, start=None, end=None):
+        """Record torch.cuda.Event `start`/`end` around kernel `kernel` of every
+        subsequent run (None clears)."""
+        sp = ctypes.c_void_p(start.cuda_event) if start is not None else None
+        ep = ctypes.c_void_p(end.cuda_event) if end is not None else None
+        _check(lib().skel_plan_kernel_events(self._h, kernel if start is not None else -1, sp, ep))
+
     def destroy(self):
         h, self._h = getattr(self, "_h", None), None
         if h and _lib is not None:
@@ -292,13 +318,21 @@ def init(device: int = 0):
 
 
 # ------------------------------------------------------- tuning / cost model
-def tune(root: Node, args, db_path: str | None = None, reps: int = 10):
+def tune(root: Node, args, db_path: str | None = None, reps: int = 10, max_configs: int = 0,
+         sample_seed: int = 0):
     arr, n = _buf_array(args)
     best = PlanOpts()
     us = ctypes.c_double()
-    _check(lib().skel_tune(root.handle, arr, n, db_path.encode() if db_path else None, reps,
-                           ctypes.byref(best), ctypes.byref(us)))
+    _check(lib().skel_tune(root.handle, arr, n, db_path.encode() if db_path else None, reps, max_configs,
+                           sample_seed, ctypes.byref(best), ctypes.byref(us)))
     return best.as_dict(), us.value
+
+
+def config_count(root: Node, protos) -> int:
+    arr, n = _buf_array(protos)
+    c = ctypes.c_int32()
+    _check(lib().skel_config_count(root.handle, arr, n, ctypes.byref(c)))
+    return c.value
 
 
 def features(root: Node, protos, options=None) -> np.ndarray:

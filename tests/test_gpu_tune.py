@@ -20,6 +20,7 @@ def test_tune_image_chain(tmp_path):
     root = sk.image_chain(st, "hist_sum")
     db = str(tmp_path / "db.csv")
     best, us = sk.tune(root, args, db, reps=3)
+    assert sk.config_count(root, args) == len(open(db).readlines())
     rows = [l.strip().split(",") for l in open(db)]
     assert len(rows) >= 8 and us > 0
     times = [float(r[-2]) for r in rows]
