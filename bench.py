@@ -54,18 +54,58 @@ def timed_runs(fn, steps, warmup):
     return time.perf_counter() - t0, e0.elapsed_time(e1)
 
 
+def _loaded_hip_runtime():
+    """The HIP runtime library already mapped into this process (the one the
+    skeleton library and torch use), opened by its exact path."""
+    import ctypes
+    for line in open("/proc/self/maps"):
+        if "libamdhip64.so" in line:
+            return ctypes.CDLL(line.split()[-1])
+    raise RuntimeError("HIP runtime not loaded")
+
+
+class HipEvents:
+    """hipEvent_t pairs from the HIP runtime (the plan records them itself, so
+    they bypass torch's event bookkeeping)."""
+
+    def __init__(self, n):
+        import ctypes
+        self.hip = _loaded_hip_runtime()
+        self.ct = ctypes
+        self.ev = []
+        for _ in range(2 * n):
+            e = ctypes.c_void_p()
+            assert self.hip.hipEventCreate(ctypes.byref(e)) == 0
+            self.ev.append(e.value)
+
+    def pair(self, i):
+        return self.ev[2 * i], self.ev[2 * i + 1]
+
+    def ms(self, i):
+        f = self.ct.c_float()
+        a, b = self.pair(i)
+        assert self.hip.hipEventSynchronize(self.ct.c_void_p(b)) == 0
+        assert self.hip.hipEventElapsedTime(self.ct.byref(f), self.ct.c_void_p(a), self.ct.c_void_p(b)) == 0
+        return f.value
+
+    def close(self):
+        for e in self.ev:
+            self.hip.hipEventDestroy(self.ct.c_void_p(e))
+
+
 def kernel_ms(plan, bound, kernel, steps):
     """Average duration of one kernel of a plan, from HIP events the plan
     records around that kernel on the launch stream."""
     import torch
-    starts = [torch.cuda.Event(enable_timing=True) for _ in range(steps)]
-    ends = [torch.cuda.Event(enable_timing=True) for _ in range(steps)]
+    ev = HipEvents(steps)
     for i in range(steps):
-        plan.kernel_events(kernel, starts[i], ends[i])
+        plan.kernel_events(kernel, *ev.pair(i))
         plan.run(bound)
     torch.cuda.synchronize()
     plan.kernel_events(-1)
-    return sum(s.elapsed_time(e) for s, e in zip(starts, ends)) / steps
+    ms = sum(ev.ms(i) for i in range(steps)) / steps
+    ev.close()
+    return ms
 
 
 def traffic_for(kernel: str, algo_bytes: float):

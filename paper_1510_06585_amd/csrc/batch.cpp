@@ -147,6 +147,7 @@ extern "C" skel_status skel_batch_run(skel_plan p, const skel_buffer* args, int3
     A.in_flip = K.img.in_flip;
     A.out_flip = K.img.out_flip;
     A.has_hist = red >= 0;
+    A.hist_ks = hist_copies_log2(K.bins, kHistWaveWords);
     A.counter = p->d_counter;
     A.pre = K.img.pre;
     A.post = K.img.post;

@@ -87,6 +87,7 @@ struct Kernel {
     VecGroupArgs vec{};        // vector kernels
     std::vector<int> side_args;
     int grid = 0, wg = 0;
+    int bins = 256;            // exclusive bound of the values this kernel emits
     const char* name = "";
 };
 

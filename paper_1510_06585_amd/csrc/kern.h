@@ -37,8 +37,18 @@ struct ImgGroupArgs {
     int32_t ntiles;      // nbands * ceil(H / tile_h)
     int32_t in_flip, out_flip;
     int32_t write_out;   // 0 for a reduce-only kernel
+    int32_t hist_ks;     // log2 of the histogram copies per bin (see hist_copies_log2)
     OpList pre, post;
 };
+
+// Output values of a kernel are < bins (128 when the chain's last value stage
+// is a solarise, else 256); the LDS histogram keeps copies = words / bins
+// counters per bin, one per lane class, so equal values in neighbouring lanes
+// hit different words and banks.  Returns log2(copies) for a per-channel
+// region of `words` counters.
+int hist_copies_log2(int bins, int words);
+constexpr int kHistWgWords = 2048;     // per channel, one histogram per work-group
+constexpr int kHistWaveWords = 512;    // per channel, one histogram per wavefront
 
 // Compile-time encoding of a value-stage run for specialised kernels:
 // sum of op_k * 4^k; -1 selects the generic stage interpreter.
@@ -72,6 +82,7 @@ struct BatchArgs {
     int32_t has_blur;
     int32_t in_flip, out_flip;
     int32_t has_hist;
+    int32_t hist_ks;     // log2 copies per bin of the per-wavefront histograms
     uint32_t* counter;   // work-queue ticket counter (zeroed before launch)
     OpList pre, post;
 };

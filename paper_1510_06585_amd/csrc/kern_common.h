@@ -4,6 +4,7 @@
 #include <stdint.h>
 
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
 typedef unsigned short u16x2 __attribute__((ext_vector_type(2)));
 
 // Raw buffer resource word 3 for gfx9-family parts (32-bit data format).
@@ -23,6 +24,9 @@ static __device__ __forceinline__ uint32_t ld32(__amdgpu_buffer_rsrc_t r, uint32
 }
 static __device__ __forceinline__ void st128(u32x4 v, __amdgpu_buffer_rsrc_t r, uint32_t off) {
     __builtin_amdgcn_raw_buffer_store_b128(v, r, off, 0, 0);
+}
+static __device__ __forceinline__ void st64(u32x2 v, __amdgpu_buffer_rsrc_t r, uint32_t off) {
+    __builtin_amdgcn_raw_buffer_store_b64(v, r, off, 0, 0);
 }
 static __device__ __forceinline__ void st32(uint32_t v, __amdgpu_buffer_rsrc_t r, uint32_t off) {
     __builtin_amdgcn_raw_buffer_store_b32(v, r, off, 0, 0);

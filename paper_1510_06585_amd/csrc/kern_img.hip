@@ -19,6 +19,8 @@
 #include "kern_common.h"
 #include "kern.h"
 
+#include <type_traits>
+
 namespace skel {
 
 // MurmurHash3 32-bit finaliser, written from its public description.
@@ -49,11 +51,40 @@ static __device__ __forceinline__ uint32_t sol_half(uint32_t v) {
     return as32(__builtin_elementwise_min(t, (u16x2)255 - t));
 }
 
+// Noise followed by solarise on one u16 pair.  With t = v + n, n in [-16, 16],
+// solarise(clamp(t, 0, 255)) == max(0, min(t, 255 - t)) for every t in
+// [-16, 271]; in unsigned form with t' = t + 16 that is
+// min(sat(t' - 16), sat(271 - t')), three packed ops instead of four.
+static __device__ __forceinline__ uint32_t noise_sol_half(uint32_t v, uint32_t hb) {
+    const u16x2 b = as16(hb);
+    const u16x2 q = (b * (u16x2)249) >> (u16x2)13;
+    const u16x2 t = as16(v) + (b - q * (u16x2)33);          // t' = v + n + 16 in [0, 287]
+    const u16x2 lo = __builtin_elementwise_sub_sat(t, (u16x2)16);
+    const u16x2 hi = __builtin_elementwise_sub_sat((u16x2)271, t);
+    return as32(__builtin_elementwise_min(lo, hi));
+}
+
+// Bytes 1 and 3 of v as a u16 pair (bytes 0 and 2 are v & 0x00FF00FF).
+static __device__ __forceinline__ uint32_t odd_bytes(uint32_t v) {
+    return __builtin_amdgcn_perm(0u, v, 0x0C030C01u);
+}
+
+static __device__ __forceinline__ uint32_t px_hash(uint32_t seed, uint32_t x, uint32_t y) {
+    return fmix32(seed ^ ((y << 16) | x));
+}
+
 static __device__ __forceinline__ void noise_px(uint32_t& e, uint32_t& o, uint32_t seed, uint32_t x,
                                                 uint32_t y) {
-    const uint32_t h = fmix32(seed ^ ((y << 16) | x));
+    const uint32_t h = px_hash(seed, x, y);
     e = noise_half(e, h & 0x00FF00FFu);
-    o = noise_half(o, (h >> 8) & 0x00FF00FFu);
+    o = noise_half(o, odd_bytes(h));
+}
+
+static __device__ __forceinline__ void noise_sol_px(uint32_t& e, uint32_t& o, uint32_t seed, uint32_t x,
+                                                    uint32_t y) {
+    const uint32_t h = px_hash(seed, x, y);
+    e = noise_sol_half(e, h & 0x00FF00FFu);
+    o = noise_sol_half(o, odd_bytes(h));
 }
 
 struct Px4 {
@@ -65,7 +96,17 @@ template <int ENC, int K>
 static __device__ __forceinline__ void apply_const(const OpList& L, Px4& p, const int (&xc)[4], int y, int W) {
     if constexpr (ENC != 0) {
         constexpr int op = ENC & 3;
-        if constexpr (op == IOP_NOISE) {
+        if constexpr (op == IOP_NOISE && ((ENC >> 2) & 3) == IOP_SOL) {
+            const uint32_t seed = L.seed[K];
+            const bool fl = L.flip[K] != 0;
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int x = fl ? (W - 1 - xc[i]) : xc[i];
+                noise_sol_px(p.e[i], p.o[i], seed, (uint32_t)x, (uint32_t)y);
+            }
+            apply_const<(ENC >> 4), K + 2>(L, p, xc, y, W);
+            return;
+        } else if constexpr (op == IOP_NOISE) {
             const uint32_t seed = L.seed[K];
             const bool fl = L.flip[K] != 0;
 #pragma unroll
@@ -91,7 +132,16 @@ static __device__ __forceinline__ void apply_ops(const OpList& L, Px4& p, const 
         // below is uniform across the wavefront.
         for (int k = 0; k < L.n; ++k) {
             const int op = L.op[k];
-            if (op == IOP_NOISE) {
+            if (op == IOP_NOISE && k + 1 < L.n && L.op[k + 1] == IOP_SOL) {
+                const uint32_t seed = L.seed[k];
+                const bool fl = L.flip[k] != 0;
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    const int x = fl ? (W - 1 - xc[i]) : xc[i];
+                    noise_sol_px(p.e[i], p.o[i], seed, (uint32_t)x, (uint32_t)y);
+                }
+                ++k;
+            } else if (op == IOP_NOISE) {
                 const uint32_t seed = L.seed[k];
                 const bool fl = L.flip[k] != 0;
 #pragma unroll
@@ -112,13 +162,25 @@ static __device__ __forceinline__ void apply_ops(const OpList& L, Px4& p, const 
     }
 }
 
-// floor(s / 25) for each u16 half, s <= 6375: (s * 5243) >> 17 is exact there.
+// floor(s / 25) for each u16 half, s <= 6375: (s * 671089) >> 24 is exact
+// there and the product fits 32 bits, so each quotient lands in byte 3 of a
+// 24-bit multiply and one byte permute gathers both into a u16 pair.
 static __device__ __forceinline__ uint32_t div25_pair(uint32_t s) {
-    const uint32_t lo = s & 0xFFFFu, hi = s >> 16;
-    return ((lo * 5243u) >> 17) | (((hi * 5243u) >> 17) << 16);
+    const uint32_t mlo = (s & 0xFFFFu) * 671089u, mhi = (s >> 16) * 671089u;
+    return __builtin_amdgcn_perm(mhi, mlo, 0x0C070C03u);
 }
 
 static __device__ __forceinline__ int clampi(int v, int lo, int hi) { return v < lo ? lo : (v > hi ? hi : v); }
+
+// Input rows in flight per wavefront ahead of the row being computed.
+constexpr int kPrefetch = 4;
+
+// Histogram modes: none, one privatised histogram per work-group, one per
+// wavefront (persistent batched kernel).  Per channel a work-group histogram
+// has kHistWgChan counter words = bins x copies, a wavefront one kHistWaveChan.
+enum { HIST_NONE = 0, HIST_WG = 1, HIST_WAVE = 2 };
+constexpr int kHistWgChan = 2048;
+constexpr int kHistWaveChan = 512;
 
 // Per-tile geometry and addressing of one image.
 struct ImgView {
@@ -141,9 +203,10 @@ static __device__ __forceinline__ void hsum5(const uint32_t (&q)[4], uint32_t (&
     h[3] = wave_shl1(t1) + q[1] + t2;
 }
 
-template <int PRE, int POST, bool BLUR, bool HIST>
+template <int PRE, int POST, bool BLUR, int HM>
 static __device__ __forceinline__ void band_tile(const ImgView& V, const OpList& pre, const OpList& post,
-                                                 int band, int y0, int y1, int lane, uint32_t* lh) {
+                                                 int band, int y0, int y1, int lane, uint32_t* lh, int hks) {
+    constexpr bool HIST = HM != HIST_NONE;
     const int W = V.W, H = V.H;
     constexpr int halo = BLUR ? 2 : 0;
     constexpr int bw = BLUR ? kBandOut : kBandPx;
@@ -155,150 +218,198 @@ static __device__ __forceinline__ void band_tile(const ImgView& V, const OpList&
     const __amdgpu_buffer_rsrc_t rin = mk_rsrc(V.in, nbytes);
     const __amdgpu_buffer_rsrc_t rout = mk_rsrc(V.out, nbytes);
 
-    int xc[4];
-    bool valid[4];
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-        xc[i] = interior ? (ub + i) : clampi(ub + i, 0, W - 1);
-        valid[i] = (ub + i >= x0) && (ub + i < xend);
-    }
-    const bool full = interior && valid[0] && valid[1] && valid[2] && valid[3];
-    const uint32_t in_vec = (uint32_t)(V.in_flip ? (W - 4 - ub) : ub) * 4u;
-    uint32_t in_px[4];
-#pragma unroll
-    for (int i = 0; i < 4; ++i) in_px[i] = (uint32_t)(V.in_flip ? (W - 1 - xc[i]) : xc[i]) * 4u;
-    const uint32_t out_vec = (uint32_t)(V.out_flip ? (W - 4 - ub) : ub) * 4u;
+    // Histogram addressing: counter (c, v, copy) lives at word
+    // c * CS + v * 2^hks + copy, copy = lane mod 2^hks; a u16 pair {v0, v1}
+    // shifted left by hks + 2 gives both byte offsets in its halves.
+    constexpr int CS = HM == HIST_WAVE ? kHistWaveChan : kHistWgChan;
+    const uint32_t hsh = (uint32_t)hks + 2u;
+    const uint32_t lane_off = ((uint32_t)lane & ((1u << hks) - 1u)) * 4u;
+    char* const lhb = reinterpret_cast<char*>(lh);
+    auto count = [&](uint32_t e, uint32_t o, uint32_t inc) {
+        const uint32_t es = e << hsh, os = o << hsh;
+        atomicAdd(reinterpret_cast<uint32_t*>(lhb + 0 * CS * 4 + lane_off + (es & 0xFFFFu)), inc);
+        atomicAdd(reinterpret_cast<uint32_t*>(lhb + 1 * CS * 4 + lane_off + (os & 0xFFFFu)), inc);
+        atomicAdd(reinterpret_cast<uint32_t*>(lhb + 2 * CS * 4 + lane_off + (es >> 16)), inc);
+        atomicAdd(reinterpret_cast<uint32_t*>(lhb + 3 * CS * 4 + lane_off + (os >> 16)), inc);
+    };
 
-    auto load_row = [&](int yy, uint32_t (&raw)[4]) {
-        const uint32_t rowoff = (uint32_t)yy * (uint32_t)W * 4u;
-        if (interior) {
-            const u32x4 v = ld128(rin, rowoff + in_vec);
-            if (V.in_flip) {
+    // The row sweep, instantiated once for interior bands (one 16-byte load
+    // and store per lane per row) and once for bands touching the image edge
+    // (clamped per-pixel loads, per-pixel stores).  Prefetched rows stay raw
+    // until consumed, so no load result is touched before its row's turn.
+    auto sweep = [&](auto interior_tag) {
+        constexpr bool I = decltype(interior_tag)::value;
+        int xc[4];
+        bool valid[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            xc[i] = I ? (ub + i) : clampi(ub + i, 0, W - 1);
+            valid[i] = (ub + i >= x0) && (ub + i < xend);
+        }
+        const bool full = I && valid[0] && valid[1] && valid[2] && valid[3];
+        // Interior blur bands: lane 0 owns output pixels 2..3 of its four and
+        // lane 63 pixels 0..1; each writes its pair with one 8-byte store.
+        const int pair0 = valid[0] ? 0 : 2;
+        const bool pair = I && !full && (valid[0] || valid[2]);
+        const uint32_t pair_off =
+            (uint32_t)(V.out_flip ? (W - 2 - (ub + pair0)) : (ub + pair0)) * 4u;
+        uint32_t inc[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) inc[i] = valid[i] ? 1u : 0u;
+        const uint32_t in_vec = (uint32_t)(V.in_flip ? (W - 4 - ub) : ub) * 4u;
+        uint32_t in_px[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) in_px[i] = (uint32_t)(V.in_flip ? (W - 1 - xc[i]) : xc[i]) * 4u;
+        const uint32_t out_vec = (uint32_t)(V.out_flip ? (W - 4 - ub) : ub) * 4u;
+
+        auto load_row = [&](int yy) -> u32x4 {
+            const uint32_t rowoff = (uint32_t)yy * (uint32_t)W * 4u;
+            if constexpr (I) {
+                return ld128(rin, rowoff + in_vec);
+            } else {
+                u32x4 r;
+                r.x = ld32(rin, rowoff + in_px[0]);
+                r.y = ld32(rin, rowoff + in_px[1]);
+                r.z = ld32(rin, rowoff + in_px[2]);
+                r.w = ld32(rin, rowoff + in_px[3]);
+                return r;
+            }
+        };
+
+        // Pixels of a loaded row in iteration order, split into channel pairs.
+        auto unpack = [&](const u32x4& v, Px4& p) {
+            uint32_t raw[4];
+            if (I && V.in_flip) {
                 raw[0] = v.w; raw[1] = v.z; raw[2] = v.y; raw[3] = v.x;
             } else {
                 raw[0] = v.x; raw[1] = v.y; raw[2] = v.z; raw[3] = v.w;
             }
-        } else {
-#pragma unroll
-            for (int i = 0; i < 4; ++i) raw[i] = ld32(rin, rowoff + in_px[i]);
-        }
-    };
-
-    auto pre_px = [&](const uint32_t (&raw)[4], int yy, Px4& p) {
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            p.e[i] = raw[i] & 0x00FF00FFu;
-            p.o[i] = (raw[i] >> 8) & 0x00FF00FFu;
-        }
-        apply_ops<PRE>(pre, p, xc, yy, W);
-    };
-
-    // Final pixels of one output row: store (mirrored if out_flip) and count.
-    auto emit = [&](const uint32_t (&fin)[4], int y) {
-        const uint32_t rowoff = (uint32_t)y * (uint32_t)W * 4u;
-        if (V.write_out) {
-            if (full) {
-                u32x4 v;
-                if (V.out_flip) {
-                    v.x = fin[3]; v.y = fin[2]; v.z = fin[1]; v.w = fin[0];
-                } else {
-                    v.x = fin[0]; v.y = fin[1]; v.z = fin[2]; v.w = fin[3];
-                }
-                st128(v, rout, rowoff + out_vec);
-            } else {
-#pragma unroll
-                for (int i = 0; i < 4; ++i)
-                    if (valid[i]) {
-                        const int u = ub + i;
-                        st32(fin[i], rout, rowoff + (uint32_t)(V.out_flip ? (W - 1 - u) : u) * 4u);
-                    }
-            }
-        }
-        if constexpr (HIST) {
-#pragma unroll
-            for (int i = 0; i < 4; ++i)
-                if (valid[i]) {
-#pragma unroll
-                    for (int c = 0; c < 4; ++c) atomicAdd(&lh[c * 256 + ((fin[i] >> (8 * c)) & 255u)], 1u);
-                }
-        }
-    };
-
-    if constexpr (!BLUR) {
-        uint32_t nxt[4];
-        load_row(y0, nxt);
-        for (int y = y0; y < y1; ++y) {
-            uint32_t raw[4];
-#pragma unroll
-            for (int i = 0; i < 4; ++i) raw[i] = nxt[i];
-            if (y + 1 < y1) load_row(y + 1, nxt);
-            Px4 p;
-            pre_px(raw, y, p);
-            uint32_t fin[4];
-#pragma unroll
-            for (int i = 0; i < 4; ++i) fin[i] = p.e[i] | (p.o[i] << 8);
-            emit(fin, y);
-        }
-    } else {
-        // Sliding 5-row window of horizontal sums: ring[s] holds the row that
-        // leaves the window next time slot s is visited.
-        uint32_t ringE[4][4], ringO[4][4];
-        uint32_t VE[4] = {0, 0, 0, 0}, VO[4] = {0, 0, 0, 0};
-        auto hrow = [&](int r, uint32_t (&hE)[4], uint32_t (&hO)[4]) {
-            const int rr = clampi(r, 0, H - 1);
-            uint32_t raw[4];
-            load_row(rr, raw);
-            Px4 p;
-            pre_px(raw, rr, p);
-            hsum5(p.e, hE);
-            hsum5(p.o, hO);
-        };
-#pragma unroll
-        for (int s = 0; s < 4; ++s) {
-            hrow(y0 - 2 + s, ringE[s], ringO[s]);
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
-                VE[i] += ringE[s][i];
-                VO[i] += ringO[s][i];
+                p.e[i] = raw[i] & 0x00FF00FFu;
+                p.o[i] = odd_bytes(raw[i]);
             }
-        }
-        uint32_t nxt[4];
-        load_row(clampi(y0 + 2, 0, H - 1), nxt);
-        for (int y = y0; y < y1; y += 4) {
+        };
+
+        // Final pixels of one output row (e/o = their channel pairs): store
+        // (mirrored if out_flip) and count.
+        auto emit = [&](const Px4& q, int y) {
+            uint32_t fin[4];
 #pragma unroll
-            for (int k = 0; k < 4; ++k) {
-                const int yy = y + k;
-                if (yy >= y1) break;
-                uint32_t raw[4];
+            for (int i = 0; i < 4; ++i) fin[i] = q.e[i] | (q.o[i] << 8);
+            const uint32_t rowoff = (uint32_t)y * (uint32_t)W * 4u;
+            if (V.write_out) {
+                if (full) {
+                    u32x4 v;
+                    if (V.out_flip) {
+                        v.x = fin[3]; v.y = fin[2]; v.z = fin[1]; v.w = fin[0];
+                    } else {
+                        v.x = fin[0]; v.y = fin[1]; v.z = fin[2]; v.w = fin[3];
+                    }
+                    st128(v, rout, rowoff + out_vec);
+                } else if (pair) {
+                    const uint32_t a = pair0 ? fin[2] : fin[0];
+                    const uint32_t b = pair0 ? fin[3] : fin[1];
+                    u32x2 v;
+                    v.x = V.out_flip ? b : a;
+                    v.y = V.out_flip ? a : b;
+                    st64(v, rout, rowoff + pair_off);
+                } else {
 #pragma unroll
-                for (int i = 0; i < 4; ++i) raw[i] = nxt[i];
-                if (yy + 1 < y1) load_row(clampi(yy + 3, 0, H - 1), nxt);
-                const int rr = clampi(yy + 2, 0, H - 1);
+                    for (int i = 0; i < 4; ++i)
+                        if (valid[i]) {
+                            const int u = ub + i;
+                            st32(fin[i], rout, rowoff + (uint32_t)(V.out_flip ? (W - 1 - u) : u) * 4u);
+                        }
+                }
+            }
+            if constexpr (HIST) {
+                // Invalid pixels add 0: no branch on per-lane validity.
+#pragma unroll
+                for (int i = 0; i < 4; ++i) count(q.e[i], q.o[i], inc[i]);
+            }
+        };
+
+        if constexpr (!BLUR) {
+            // Rows are prefetched kPrefetch ahead; slot k of the unrolled loop
+            // is refilled as soon as it is consumed (the refill index is
+            // clamped to the tile, so the last rows re-read cached lines).
+            u32x4 nxt[kPrefetch];
+#pragma unroll
+            for (int d = 0; d < kPrefetch; ++d) nxt[d] = load_row(min(y0 + d, y1 - 1));
+            for (int y = y0; y < y1; y += kPrefetch) {
+#pragma unroll
+                for (int k = 0; k < kPrefetch; ++k) {
+                    const int yy = y + k;
+                    if (yy >= y1) break;
+                    Px4 p;
+                    unpack(nxt[k], p);                               // slot consumed ...
+                    nxt[k] = load_row(min(yy + kPrefetch, y1 - 1));  // ... and refilled in place
+                    apply_ops<PRE>(pre, p, xc, yy, W);
+                    emit(p, yy);
+                }
+            }
+        } else {
+            // Sliding 5-row window of horizontal sums: ring[s] holds the row
+            // that leaves the window next time slot s is visited.
+            uint32_t ringE[4][4], ringO[4][4];
+            uint32_t VE[4] = {0, 0, 0, 0}, VO[4] = {0, 0, 0, 0};
+#pragma unroll
+            for (int s = 0; s < 4; ++s) {
+                const int rr = clampi(y0 - 2 + s, 0, H - 1);
                 Px4 p;
-                pre_px(raw, rr, p);
-                uint32_t hE[4], hO[4];
-                hsum5(p.e, hE);
-                hsum5(p.o, hO);
-                Px4 q;
+                unpack(load_row(rr), p);
+                apply_ops<PRE>(pre, p, xc, rr, W);
+                hsum5(p.e, ringE[s]);
+                hsum5(p.o, ringO[s]);
 #pragma unroll
                 for (int i = 0; i < 4; ++i) {
-                    const uint32_t fe = VE[i] + hE[i];
-                    const uint32_t fo = VO[i] + hO[i];
-                    VE[i] = fe - ringE[k][i];
-                    VO[i] = fo - ringO[k][i];
-                    ringE[k][i] = hE[i];
-                    ringO[k][i] = hO[i];
-                    q.e[i] = div25_pair(fe);
-                    q.o[i] = div25_pair(fo);
+                    VE[i] += ringE[s][i];
+                    VO[i] += ringO[s][i];
                 }
-                apply_ops<POST>(post, q, xc, yy, W);
-                uint32_t fin[4];
+            }
+            // Input rows y+2 ... are prefetched kPrefetch ahead (kPrefetch
+            // divides the unroll factor 4, so every slot index is a constant);
+            // refills are clamped to the last row the tile needs, y1 + 1.
+            const int last = min(y1 + 1, H - 1);
+            u32x4 nxt[kPrefetch];
 #pragma unroll
-                for (int i = 0; i < 4; ++i) fin[i] = q.e[i] | (q.o[i] << 8);
-                emit(fin, yy);
+            for (int d = 0; d < kPrefetch; ++d) nxt[d] = load_row(min(y0 + 2 + d, last));
+            for (int y = y0; y < y1; y += 4) {
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    const int yy = y + k;
+                    if (yy >= y1) break;
+                    const int rr = min(yy + 2, H - 1);
+                    Px4 p;
+                    unpack(nxt[k % kPrefetch], p);                               // slot consumed ...
+                    nxt[k % kPrefetch] = load_row(min(yy + 2 + kPrefetch, last));  // ... refilled in place
+                    apply_ops<PRE>(pre, p, xc, rr, W);
+                    uint32_t hE[4], hO[4];
+                    hsum5(p.e, hE);
+                    hsum5(p.o, hO);
+                    Px4 q;
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) {
+                        const uint32_t fe = VE[i] + hE[i];
+                        const uint32_t fo = VO[i] + hO[i];
+                        VE[i] = fe - ringE[k][i];
+                        VO[i] = fo - ringO[k][i];
+                        ringE[k][i] = hE[i];
+                        ringO[k][i] = hO[i];
+                        q.e[i] = div25_pair(fe);
+                        q.o[i] = div25_pair(fo);
+                    }
+                    apply_ops<POST>(post, q, xc, yy, W);
+                    emit(q, yy);
+                }
             }
         }
-    }
+    };
+    if (interior)
+        sweep(std::true_type{});
+    else
+        sweep(std::false_type{});
 }
 
 static __device__ __forceinline__ uint64_t wave_sum_u64(uint64_t v) {
@@ -311,21 +422,27 @@ static __device__ __forceinline__ uint64_t wave_sum_u64(uint64_t v) {
     return v;
 }
 
-// Merges an LDS histogram (4 x 256 counts) into the global histogram and
-// channel sums by addition (the merge function of Sec. 3.4).  `first`/`step`
-// select the bins this thread handles; lanes of one wavefront must cover
-// disjoint bins.  Channel sums are derived from the counts.
-static __device__ __forceinline__ void flush_hist(const uint32_t* lh, uint32_t* hist, uint64_t* sum, int first,
-                                                  int step, int lane) {
+// Merges a privatised LDS histogram into the global histogram and channel
+// sums by addition (the merge function of Sec. 3.4).  Counter (c, v, copy)
+// is at word c * CS + v * 2^hks + copy; the 2^hks copies of a bin are added
+// first.  `first`/`step` select the bins this thread handles; the lanes of a
+// wavefront cover disjoint bins.  Channel sums are derived from the counts.
+template <int CS>
+static __device__ __forceinline__ void flush_hist(const uint32_t* lh, int hks, uint32_t* hist, uint64_t* sum,
+                                                  int first, int step, int lane) {
+    const int copies = 1 << hks;
+    const int bins = CS >> hks;
     uint64_t s[4];
 #pragma unroll
     for (int c = 0; c < 4; ++c) {
         s[c] = 0;
-        for (int b = first; b < 256; b += step) {
-            const uint32_t n = lh[c * 256 + b];
+        for (int v = first; v < bins; v += step) {
+            const uint32_t* w = lh + c * CS + (v << hks);
+            uint32_t n = 0;
+            for (int j = 0; j < copies; ++j) n += w[(j + v) & (copies - 1)];
             if (n) {
-                if (hist) atomicAdd(&hist[c * 256 + b], n);
-                s[c] += (uint64_t)b * n;
+                if (hist) atomicAdd(&hist[c * 256 + v], n);
+                s[c] += (uint64_t)v * n;
             }
         }
     }
@@ -338,12 +455,12 @@ static __device__ __forceinline__ void flush_hist(const uint32_t* lh, uint32_t* 
 
 template <int PRE, int POST, bool BLUR, bool HIST>
 __global__ void __launch_bounds__(256) img_band_kernel(const ImgGroupArgs A) {
-    __shared__ uint32_t lh[HIST ? 1024 : 1];
+    __shared__ uint32_t lh[HIST ? 4 * kHistWgChan : 1];
     const int lane = threadIdx.x & 63;
     const int nw = blockDim.x >> 6;
     const int wave = wave_uniform(threadIdx.x >> 6);
     if constexpr (HIST) {
-        for (int b = threadIdx.x; b < 1024; b += blockDim.x) lh[b] = 0;
+        for (int b = threadIdx.x; b < 4 * kHistWgChan; b += blockDim.x) lh[b] = 0;
         __syncthreads();
     }
     const int tile = blockIdx.x * nw + wave;
@@ -353,11 +470,12 @@ __global__ void __launch_bounds__(256) img_band_kernel(const ImgGroupArgs A) {
         const int y0 = chunk * A.tile_h;
         const int y1 = min(y0 + A.tile_h, A.H);
         const ImgView V{A.in, A.out, A.W, A.H, A.in_flip, A.out_flip, A.write_out};
-        band_tile<PRE, POST, BLUR, HIST>(V, A.pre, A.post, band, y0, y1, lane, lh);
+        band_tile<PRE, POST, BLUR, HIST ? HIST_WG : HIST_NONE>(V, A.pre, A.post, band, y0, y1, lane, lh,
+                                                                A.hist_ks);
     }
     if constexpr (HIST) {
         __syncthreads();
-        flush_hist(lh, A.hist, A.sum, threadIdx.x, blockDim.x, lane);
+        flush_hist<kHistWgChan>(lh, A.hist_ks, A.hist, A.sum, threadIdx.x, blockDim.x, lane);
     }
 }
 
@@ -367,10 +485,10 @@ __global__ void __launch_bounds__(256) img_band_kernel(const ImgGroupArgs A) {
 // tile and merges its own LDS histogram into that request's outputs.
 template <int PRE, int POST, bool BLUR, bool HIST>
 __global__ void __launch_bounds__(256) img_batch_kernel(const BatchArgs A) {
-    __shared__ uint32_t lh_all[HIST ? 4 * 1024 : 1];
+    __shared__ uint32_t lh_all[HIST ? 4 * 4 * kHistWaveChan : 1];
     const int lane = threadIdx.x & 63;
     const int wave = wave_uniform(threadIdx.x >> 6);
-    uint32_t* lh = HIST ? lh_all + wave * 1024 : lh_all;
+    uint32_t* lh = HIST ? lh_all + wave * 4 * kHistWaveChan : lh_all;
     for (;;) {
         uint32_t t = 0;
         if (lane == 0) t = atomicAdd(A.counter, 1u);
@@ -388,16 +506,17 @@ __global__ void __launch_bounds__(256) img_batch_kernel(const BatchArgs A) {
         const int y0 = chunk * A.tile_h;
         const int y1 = min(y0 + A.tile_h, R.H);
         if constexpr (HIST) {
-            for (int b = lane; b < 1024; b += 64) lh[b] = 0;
+            for (int b = lane; b < 4 * kHistWaveChan; b += 64) lh[b] = 0;
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
             __builtin_amdgcn_wave_barrier();
         }
         const ImgView V{R.in, R.out, R.W, R.H, A.in_flip, A.out_flip, 1};
-        band_tile<PRE, POST, BLUR, HIST>(V, A.pre, A.post, band, y0, y1, lane, lh);
+        band_tile<PRE, POST, BLUR, HIST ? HIST_WAVE : HIST_NONE>(V, A.pre, A.post, band, y0, y1, lane, lh,
+                                                                  A.hist_ks);
         if constexpr (HIST) {
             __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
             __builtin_amdgcn_wave_barrier();
-            flush_hist(lh, R.hist, R.sum, lane, 64, lane);
+            flush_hist<kHistWaveChan>(lh, A.hist_ks, R.hist, R.sum, lane, 64, lane);
             __builtin_amdgcn_wave_barrier();
         }
     }
@@ -419,6 +538,14 @@ __global__ void fill_u32_kernel(uint32_t* p, uint64_t n, uint32_t v) {
 }
 
 // ------------------------------------------------------------------ host side
+static_assert(kHistWgChan == kHistWgWords && kHistWaveChan == kHistWaveWords, "histogram layout");
+
+int hist_copies_log2(int bins, int words) {
+    int ks = 0;
+    while ((bins << (ks + 1)) <= words) ++ks;
+    return ks;
+}
+
 int encode_ops(const OpList& l) {
     int e = 0, m = 1;
     for (int k = 0; k < l.n; ++k) {

@@ -347,8 +347,20 @@ static void push_op(OpList& l, const Stage& s, int flip) {
     l.seed[k] = s.prm.seed;
 }
 
+// Exclusive upper bound of the final image's values: 128 when the last stage
+// that changes values is a solarise (min(v, 255 - v) <= 127, and blur and
+// mirror never raise a maximum), else 256.
+static int final_value_bins(const Linear& L) {
+    for (int i = (int)L.st.size() - 1; i >= 0; --i) {
+        if (L.st[i].op == SKEL_OP_SOLARISE) return 128;
+        if (L.st[i].op == SKEL_OP_NOISE) return 256;
+    }
+    return 256;
+}
+
 skel_status build_kernels(const Linear& L, const Shape& sh, const Config& c, std::vector<Kernel>& ks) {
     ks.clear();
+    const int bins = final_value_bins(L);
     if (L.dom == DOM_NBODY) {
         Kernel k;
         k.first = 0;
@@ -411,6 +423,8 @@ skel_status build_kernels(const Linear& L, const Shape& sh, const Config& c, std
             const int64_t chunks = (sh.H + c.tile_h - 1) / c.tile_h;
             A.ntiles = (sh.W == 0 || sh.H == 0) ? 0 : (int32_t)(A.nbands * chunks);
             A.write_out = 1;
+            A.hist_ks = hist_copies_log2(bins, kHistWgWords);
+            K.bins = bins;
             K.grid = (A.ntiles + c.wg / 64 - 1) / (c.wg / 64);
             K.name = img_kernel_name(A, K.blur, K.reduce, c.variant);
         } else {
@@ -455,6 +469,7 @@ skel_status build_kernels(const Linear& L, const Shape& sh, const Config& c, std
             const int64_t chunks = (sh.H + c.tile_h - 1) / c.tile_h;
             A.ntiles = (sh.W == 0 || sh.H == 0) ? 0 : (int32_t)(A.nbands * chunks);
             A.write_out = 0;
+            A.hist_ks = hist_copies_log2(bins, kHistWgWords);
             R.grid = (A.ntiles + c.wg / 64 - 1) / (c.wg / 64);
             R.name = img_kernel_name(A, false, true, c.variant);
         } else {

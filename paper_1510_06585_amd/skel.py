@@ -294,11 +294,14 @@ class Plan:
         return json.loads(buf.value.decode())
 
     def kernel_events(self, kernel: int, start=None, end=None):
-        """Record torch.cuda.Event `start`/`end` around kernel `kernel` of every
-        subsequent run (None clears)."""
-        sp = ctypes.c_void_p(start.cuda_event) if start is not None else None
-        ep = ctypes.c_void_p(end.cuda_event) if end is not None else None
-        _check(lib().skel_plan_kernel_events(self._h, kernel if start is not None else -1, sp, ep))
+        """Record hipEvent_t `start`/`end` (raw handles, or objects with a
+        `cuda_event` handle) around kernel `kernel` of every subsequent run;
+        None clears the hook."""
+        def h(e):
+            if e is None:
+                return None
+            return ctypes.c_void_p(e if isinstance(e, int) else e.cuda_event)
+        _check(lib().skel_plan_kernel_events(self._h, kernel if start is not None else -1, h(start), h(end)))
 
     def destroy(self):
         h, self._h = getattr(self, "_h", None), None

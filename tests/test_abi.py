@@ -169,4 +169,5 @@ def test_kernel_constants_exact():
     # constants the image kernels use in place of divisions
     assert all(b - 33 * ((b * 249) >> 13) == b % 33 for b in range(256))
     assert all((s * 5243) >> 17 == s // 25 for s in range(25 * 255 + 1))
+    assert all((s * 671089) >> 24 == s // 25 for s in range(25 * 255 + 1)) and 6375 * 671089 < 2 ** 32
     assert all(b * 249 < 65536 for b in range(256))
