@@ -26,7 +26,7 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0                                   # MI355X HBM3E, GB/s
 VALU_LANE_OPS = 256 * 64 * 2.4e9                        # 256 CUs x 64 lanes x 2.4 GHz
-NBODY_LANE_OPS_PER_PAIR = 16                            # 12 VALU + v_rsq_f32 (quarter rate)
+NBODY_LANE_OPS_PER_PAIR = 13                            # 13 VALU issues per pair, v_rsq_f32 included
 METRIC = "Gelem/s & % HBM roofline per skeleton; fused/learned vs plain speedup"
 CFG2 = [("noise", {"seed": 0x1510}), ("solarise", {}), ("blur5", {}), ("mirror", {})]
 CFG1 = [("noise", {"seed": 0x1510}), ("solarise", {}), ("mirror", {})]
@@ -165,6 +165,10 @@ def bench_config2(steps, warmup, do_cpu):
     k_ms = kernel_ms(fused, bound, 0, steps)
     _, plain_ms = timed_runs(lambda: plain.run(bound), max(5, steps // 4), 3)
     plain_ms /= max(5, steps // 4)
+    # Context: a device-to-device copy of the same image through torch.
+    src, dst = args[0], args[1]
+    _, copy_ms = timed_runs(lambda: dst.copy_(src), 50, 5)
+    copy_gbs = 2.0 * H * W * 4 / (copy_ms / 50 * 1e-3) / 1e9
     desc = fused.describe()
     algo = 2.0 * H * W * 4 + 4 * 256 * 4 + 4 * 8      # read + write image, hist + sums
     achieved = algo / (k_ms * 1e-3) / 1e9
@@ -190,6 +194,7 @@ def bench_config2(steps, warmup, do_cpu):
         "roofline": {"bound": "hbm", "kernel": kname, "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": traffic, "kernel_ms": round(k_ms, 5), "algorithmic_bytes": int(algo)},
+        "copy_reference_gbs": round(copy_gbs, 1),
         "event_ms_per_step": round(ev_ms / steps, 5),
         "plain_ms_per_step": round(plain_ms, 5),
         "fused_vs_plain_speedup": round(plain_ms / (ev_ms / steps), 3),
@@ -240,7 +245,7 @@ def bench_nbody():
     peak = VALU_LANE_OPS / NBODY_LANE_OPS_PER_PAIR
     res["roofline"] = {"bound": "alu", "achieved": round(rate / 1e9, 2), "peak": round(peak / 1e9, 2),
                        "unit": "Ginteractions/s", "frac": round(rate / peak, 4),
-                       "note": "peak = 256 CUs x 64 lanes x 2.4 GHz / 16 lane-cycles per pair"}
+                       "note": "peak = 256 CUs x 64 lanes x 2.4 GHz / 13 VALU issues per pair"}
     res["tflops_20flop_convention"] = round(rate * 20 / 1e12, 2)
     return res
 
@@ -310,6 +315,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--selector", action="store_true", help="run the learned-selector experiment instead")
     ap.add_argument("--profile-run", action="store_true", help="short run for rocprofv3 counter passes")
+    ap.add_argument("--selector-dir", default=None, help="where the selector experiment keeps its databases")
+    ap.add_argument("--selector-train", type=int, default=1000)
+    ap.add_argument("--selector-test", type=int, default=200)
     a = ap.parse_args()
     if a.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {a.gpus}); multi-GPU runs are not part "
@@ -327,7 +335,8 @@ def main():
         return
     if a.selector:
         from paper_1510_06585_amd import selector
-        print(json.dumps(selector.experiment()), flush=True)
+        print(json.dumps(selector.experiment(n_train=a.selector_train, n_test=a.selector_test,
+                                             workdir=a.selector_dir, log=log)), flush=True)
         return
     log("config 2: fused pipeline + mapreduce 8192x8192")
     out, img = bench_config2(a.steps, a.warmup, not a.no_cpu_baseline)

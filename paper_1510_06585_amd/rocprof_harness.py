@@ -1,0 +1,125 @@
+"""rocprofv3 harness: turns kernel-trace statistics and hardware-counter passes
+into the short text summaries kept under ``profiles/``.
+
+The counter passes are taken one counter group per run (rocprofv3 does not
+split counters over passes):
+
+  rocprofv3 --kernel-trace --stats -d DIR -o cfg2 --output-format csv -- python3 bench.py \
+      --steps 20 --warmup 5 --no-extras --no-cpu-baseline
+  rocprofv3 --pmc FETCH_SIZE -d DIR -o fetch --output-format csv -- python3 bench.py --profile-run --steps 5
+  rocprofv3 --pmc WRITE_SIZE -d DIR -o write --output-format csv -- python3 bench.py --profile-run --steps 5
+  rocprofv3 --pmc SQ_WAVES SQ_INSTS_VALU SQ_INSTS_LDS SQ_LDS_BANK_CONFLICT SQ_ACTIVE_INST_VALU \
+      SQ_ACTIVE_INST_LDS SQ_BUSY_CYCLES SQ_WAVE_CYCLES -d DIR -o sq --output-format csv -- \
+      python3 bench.py --profile-run --steps 3
+
+``bench.py --profile-run`` launches the fused 8192^2 kernel and a plain copy of
+the same image; FETCH_SIZE / WRITE_SIZE (KiB per dispatch) of the fused kernel
+are scaled by (known bytes / counter reading) of the copy kernel, which
+corrects for the share of the memory channels the counters observe.
+
+  python -m paper_1510_06585_amd.rocprof_harness --trace DIR/cfg2_kernel_stats.csv \
+      --fetch DIR/fetch_counter_collection.csv --write DIR/write_counter_collection.csv \
+      --sq DIR/sq_counter_collection.csv --out profiles/
+"""
+from __future__ import annotations
+
+import argparse
+import collections
+import csv
+import hashlib
+import json
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+FUSED = "img_band_kernel<9, 0, true, true>"
+FUSED_NAME = "img_noise_sol_blur_reduce"
+COPY = "img_band_kernel<0, 0, false, false>"
+COPY_BYTES = 2 * 8192 * 8192 * 4
+COMMANDS = (
+    "rocprofv3 --kernel-trace --stats -d DIR -o cfg2 --output-format csv -- python3 bench.py "
+    "--steps 20 --warmup 5 --no-extras --no-cpu-baseline",
+    "rocprofv3 --pmc FETCH_SIZE -d DIR -o fetch --output-format csv -- python3 bench.py --profile-run --steps 5",
+    "rocprofv3 --pmc WRITE_SIZE -d DIR -o write --output-format csv -- python3 bench.py --profile-run --steps 5",
+    "rocprofv3 --pmc SQ_WAVES SQ_INSTS_VALU SQ_INSTS_LDS SQ_LDS_BANK_CONFLICT SQ_ACTIVE_INST_VALU "
+    "SQ_ACTIVE_INST_LDS SQ_BUSY_CYCLES SQ_WAVE_CYCLES -d DIR -o sq --output-format csv -- "
+    "python3 bench.py --profile-run --steps 3",
+    "python -m paper_1510_06585_amd.rocprof_harness --trace DIR/cfg2_kernel_stats.csv "
+    "--fetch DIR/fetch_counter_collection.csv --write DIR/write_counter_collection.csv "
+    "--sq DIR/sq_counter_collection.csv --out profiles/",
+)
+
+
+def kernel_stats(path):
+    out = []
+    for r in csv.DictReader(open(path)):
+        out.append({"name": r["Name"], "calls": int(r["Calls"]), "avg_ns": float(r["AverageNs"]),
+                    "min_ns": float(r["MinNs"]), "max_ns": float(r["MaxNs"]),
+                    "pct": float(r["Percentage"])})
+    return out
+
+
+def counters(path):
+    agg = collections.defaultdict(lambda: collections.defaultdict(list))
+    for r in csv.DictReader(open(path)):
+        agg[r["Kernel_Name"]][r["Counter_Name"]].append(float(r["Counter_Value"]))
+    return {k: {c: sum(v) / len(v) for c, v in d.items()} for k, d in agg.items()}
+
+
+def _find(d, key):
+    for k, v in d.items():
+        if key in k:
+            return v
+    raise KeyError(key)
+
+
+def traffic(fetch_csv, write_csv):
+    """HBM bytes per launch of the fused kernel, scaled by the copy kernel."""
+    f, w = counters(fetch_csv), counters(write_csv)
+    cf, cw = _find(f, COPY)["FETCH_SIZE"], _find(w, COPY)["WRITE_SIZE"]
+    kf, kw = _find(f, FUSED)["FETCH_SIZE"], _find(w, FUSED)["WRITE_SIZE"]
+    sf = (COPY_BYTES / 2) / (cf * 1024.0)
+    sw = (COPY_BYTES / 2) / (cw * 1024.0)
+    return {"fetch_kib_raw": kf, "write_kib_raw": kw, "copy_fetch_kib_raw": cf, "copy_write_kib_raw": cw,
+            "fetch_scale": sf, "write_scale": sw,
+            "bytes_per_launch": kf * 1024.0 * sf + kw * 1024.0 * sw}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--trace", required=True)
+    ap.add_argument("--fetch", required=True)
+    ap.add_argument("--write", required=True)
+    ap.add_argument("--sq")
+    ap.add_argument("--out", required=True)
+    a = ap.parse_args()
+    os.makedirs(a.out, exist_ok=True)
+    st = kernel_stats(a.trace)
+    tr = traffic(a.fetch, a.write)
+    src = os.path.join(HERE, "csrc", "kern_img.hip")
+    rec = {"kernel": FUSED_NAME, "source": "kern_img.hip",
+           "source_sha256": hashlib.sha256(open(src, "rb").read()).hexdigest(),
+           "bytes_per_launch": round(tr["bytes_per_launch"]),
+           "algorithmic_bytes": 2 * 8192 * 8192 * 4 + 4128, **{k: round(v, 4) for k, v in tr.items()}}
+    json.dump(rec, open(os.path.join(a.out, f"traffic_{FUSED_NAME}.json"), "w"), indent=1)
+    lines = ["# rocprofv3 summary: fused Pipeline+MapReduce, 8192x8192 RGBA u8 (and the plain plan's kernels)",
+             "", "Commands (repository root on the GPU box, TMPDIR=/tmp):", "", "```"] + list(COMMANDS)
+    lines += ["```", "", "## Kernel trace (--kernel-trace --stats)", "",
+              "| kernel | calls | avg us | min us | max us |", "|---|---|---|---|---|"]
+    for r in st:
+        lines.append(f"| `{r['name'][:90]}` | {r['calls']} | {r['avg_ns']/1e3:.2f} | {r['min_ns']/1e3:.2f} | "
+                     f"{r['max_ns']/1e3:.2f} |")
+    lines += ["", "## HBM traffic per launch (FETCH_SIZE, WRITE_SIZE; scaled by a copy kernel of 512 MiB)", ""]
+    for k, v in rec.items():
+        lines.append(f"- {k}: {v}")
+    if a.sq:
+        sq = counters(a.sq)
+        lines += ["", "## SQ counters (mean per dispatch)", "", "| kernel | counter | value |", "|---|---|---|"]
+        for kern in (FUSED, COPY):
+            for c, v in sorted(_find(sq, kern).items()):
+                lines.append(f"| `{kern}` | {c} | {v:.0f} |")
+    open(os.path.join(a.out, f"{FUSED_NAME}_8192.md"), "w").write("\n".join(lines) + "\n")
+    print(json.dumps(rec))
+
+
+if __name__ == "__main__":
+    main()

@@ -114,6 +114,7 @@ def experiment(n_train: int = 1000, n_test: int = 200, per_train: int = 20, seed
     gen = torch.Generator(device="cuda")
     gen.manual_seed(seed)
     workdir = workdir or tempfile.mkdtemp(prefix="skel_selector_")
+    os.makedirs(workdir, exist_ok=True)
     train_db = os.path.join(workdir, "train.csv")
     test_db = os.path.join(workdir, "test.csv")
     for p in (train_db, test_db):
@@ -135,7 +136,7 @@ def experiment(n_train: int = 1000, n_test: int = 200, per_train: int = 20, seed
         args = _args_for(c, gen)
         sk.tune(root, args, train_db, reps=5, max_configs=per_train, sample_seed=seed * 100003 + i)
         del args
-        if i % 100 == 0:
+        if i % 50 == 0:
             log(f"train {i}/{len(train)} {time.time() - t0:.0f}s")
     n_labels = len(_read_rows(train_db))
     t_train_labels = time.time() - t0
