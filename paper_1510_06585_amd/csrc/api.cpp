@@ -421,9 +421,11 @@ skel_status skel_plan_describe(skel_plan p, char* buf, size_t len) {
     s += tmp;
     for (size_t i = 0; i < p->kernels.size(); ++i) {
         const Kernel& k = p->kernels[i];
-        snprintf(tmp, sizeof(tmp), "%s{\"name\":\"%s\",\"stages\":[%d,%d],\"blur\":%s,\"reduce\":%s,\"grid\":%d,\"wg\":%d}",
+        snprintf(tmp, sizeof(tmp),
+                 "%s{\"name\":\"%s\",\"stages\":[%d,%d],\"blur\":%s,\"reduce\":%s,\"grid\":%d,\"wg\":%d,"
+                 "\"tile_h\":%d}",
                  i ? "," : "", k.name, k.first, k.last, k.blur ? "true" : "false", k.reduce ? "true" : "false",
-                 k.grid, k.wg);
+                 k.grid, k.wg, p->lin.dom == DOM_U8 ? k.img.tile_h : p->cfg.tile_h);
         s += tmp;
     }
     snprintf(tmp, sizeof(tmp), "],\"config\":{\"fusion\":%d,\"split_mask\":%u,\"tile_h\":%d,\"wg\":%d,\"ept\":%d,\"variant\":%d}}",

@@ -67,7 +67,11 @@ struct Config {
     int wg = 0;
     int ept = 0;
     int variant = 0;
+    bool auto_tile = false;   // tile_h not given: fit each kernel's tiles to one resident round
 };
+
+// Compute units of the current device (256 when no device is visible).
+int device_cu_count();
 
 // Shape of the arguments a plan is compiled for.
 struct Shape {

@@ -62,6 +62,9 @@ hipError_t launch_img_group(const ImgGroupArgs& a, bool blur, bool hist, int wg,
                             hipStream_t s, const char** kname);
 
 const char* img_kernel_name(const ImgGroupArgs& a, bool blur, bool hist, int variant);
+// Resident wavefronts per CU of the kernel launch_img_group would pick (16
+// when the occupancy query is unavailable, e.g. without a device).
+int img_waves_per_cu(const ImgGroupArgs& a, bool blur, bool hist, int wg, int variant);
 
 // Work list entry of the batched persistent kernel (one per request).
 struct BatchReq {

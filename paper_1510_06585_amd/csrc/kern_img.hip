@@ -603,6 +603,18 @@ static const ImgEntry* find_entry(const OpList& pre, const OpList& post, bool bl
     return nullptr;
 }
 
+int img_waves_per_cu(const ImgGroupArgs& a, bool blur, bool hist, int wg, int variant) {
+    const ImgEntry* e = find_entry(a.pre, a.post, blur, hist, variant);
+    int nb = 0;
+    if (!e || hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, reinterpret_cast<const void*>(e->fn), wg, 0) !=
+                  hipSuccess ||
+        nb <= 0) {
+        (void)hipGetLastError();
+        return 16;
+    }
+    return nb * (wg / 64);
+}
+
 const char* img_kernel_name(const ImgGroupArgs& a, bool blur, bool hist, int variant) {
     const ImgEntry* e = find_entry(a.pre, a.post, blur, hist, variant);
     return e ? e->name : "";

@@ -11,6 +11,9 @@
 #include <cstdio>
 #include <cstring>
 
+#include <algorithm>
+#include <hip/hip_runtime.h>
+
 #include "internal.h"
 
 namespace skel {
@@ -257,6 +260,7 @@ skel_status resolve_config(const Linear& L, const Shape& sh, const skel_plan_opt
         if (o->tile_h) {
             c.tile_h = o->tile_h;
         } else {
+            c.auto_tile = true;
             bool blur = false;
             for (const Stage& s : L.st) blur |= s.op == SKEL_OP_BLUR5;
             const int64_t nb = (sh.W + (blur ? kBandOut : kBandPx) - 1) / (blur ? kBandOut : kBandPx);
@@ -358,6 +362,32 @@ static int final_value_bins(const Linear& L) {
     return 256;
 }
 
+int device_cu_count() {
+    static int cus = 0;
+    if (!cus) {
+        int dev = 0, n = 0;
+        if (hipGetDevice(&dev) == hipSuccess &&
+            hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && n > 0)
+            cus = n;
+        else
+            cus = 256;
+    }
+    return cus;
+}
+
+// Rows per tile such that one launch is a single round of resident
+// wavefronts: a grid larger than the resident capacity leaves a tail round of
+// a few wavefronts that runs alone.  Stencil tiles keep at least 16 rows (the
+// two halo rows above and below are recomputed per tile).
+static int fitted_tile_h(const ImgGroupArgs& A, bool blur, bool hist, const Config& c) {
+    if (A.W <= 0 || A.H <= 0) return 1;
+    const int64_t resident = (int64_t)img_waves_per_cu(A, blur, hist, c.wg, c.variant) * device_cu_count();
+    const int64_t chunks = std::max<int64_t>(1, resident / std::max<int32_t>(1, A.nbands));
+    int th = (int)((A.H + chunks - 1) / chunks);
+    th = std::max(th, blur ? 16 : 4);
+    return std::min(th, (int)A.H);
+}
+
 skel_status build_kernels(const Linear& L, const Shape& sh, const Config& c, std::vector<Kernel>& ks) {
     ks.clear();
     const int bins = final_value_bins(L);
@@ -417,10 +447,10 @@ skel_status build_kernels(const Linear& L, const Shape& sh, const Config& c, std
             }
             A.W = (int32_t)sh.W;
             A.H = (int32_t)sh.H;
-            A.tile_h = c.tile_h;
             const int bw = K.blur ? kBandOut : kBandPx;
             A.nbands = (int32_t)((sh.W + bw - 1) / bw);
-            const int64_t chunks = (sh.H + c.tile_h - 1) / c.tile_h;
+            A.tile_h = c.auto_tile ? fitted_tile_h(A, K.blur, K.reduce, c) : c.tile_h;
+            const int64_t chunks = (sh.H + A.tile_h - 1) / A.tile_h;
             A.ntiles = (sh.W == 0 || sh.H == 0) ? 0 : (int32_t)(A.nbands * chunks);
             A.write_out = 1;
             A.hist_ks = hist_copies_log2(bins, kHistWgWords);
@@ -464,9 +494,9 @@ skel_status build_kernels(const Linear& L, const Shape& sh, const Config& c, std
             memset(&A, 0, sizeof(A));
             A.W = (int32_t)sh.W;
             A.H = (int32_t)sh.H;
-            A.tile_h = c.tile_h;
             A.nbands = (int32_t)((sh.W + kBandPx - 1) / kBandPx);
-            const int64_t chunks = (sh.H + c.tile_h - 1) / c.tile_h;
+            A.tile_h = c.auto_tile ? fitted_tile_h(A, false, true, c) : c.tile_h;
+            const int64_t chunks = (sh.H + A.tile_h - 1) / A.tile_h;
             A.ntiles = (sh.W == 0 || sh.H == 0) ? 0 : (int32_t)(A.nbands * chunks);
             A.write_out = 0;
             A.hist_ks = hist_copies_log2(bins, kHistWgWords);

@@ -108,7 +108,8 @@ void features(const Linear& L, const Shape& sh, const Config& c, float* f) {
     }
     const bool any_blur = cnt[3] > 0;
     f[16] = (float)lg2(L.dom == DOM_U8 ? (any_blur ? kBandOut : kBandPx) : 4.0 * c.ept);
-    f[17] = (float)lg2(std::max(1, c.tile_h));
+    const int th = (L.dom == DOM_U8 && !ks.empty()) ? ks[0].img.tile_h : c.tile_h;
+    f[17] = (float)lg2(std::max(1, th));
     f[18] = (float)lg2(c.wg);
     f[19] = (float)lg2(std::max(1, c.ept));
     int worst = 0;
