@@ -127,18 +127,13 @@ void* resolve_img(skel_plan p, const skel_buffer* args, int id) {
 
 skel_status run_image(skel_plan p, const skel_buffer* args, hipStream_t s) {
     const Linear& L = p->lin;
-    if (L.red == SKEL_RED_HIST256_SUM) {
-        HIP_TRY(launch_fill_u32(args[2].data, 1024, 0, s));
-        HIP_TRY(launch_fill_u32(args[3].data, 8, 0, s));
-    } else if (L.red == SKEL_RED_SUM) {
-        HIP_TRY(launch_fill_u32(args[2].data, 8, 0, s));
-    }
     for (size_t ki = 0; ki < p->kernels.size(); ++ki) {
         Kernel& k = p->kernels[ki];
         ImgGroupArgs A = k.img;
         A.in = (const uint8_t*)resolve_img(p, args, k.src);
         A.out = (uint8_t*)resolve_img(p, args, k.dst);
         if (k.reduce) {
+            A.part = p->hrows;
             A.hist = L.red == SKEL_RED_HIST256_SUM ? (uint32_t*)args[2].data : nullptr;
             A.sum = L.red == SKEL_RED_HIST256_SUM ? (uint64_t*)args[3].data : (uint64_t*)args[2].data;
         }
@@ -146,6 +141,21 @@ skel_status run_image(skel_plan p, const skel_buffer* args, hipStream_t s) {
         if (prof) HIP_TRY(hipEventRecord(p->prof_start, s));
         HIP_TRY(launch_img_group(A, k.blur, k.reduce, k.wg, p->cfg.variant, s, &k.name));
         if (prof) HIP_TRY(hipEventRecord(p->prof_end, s));
+        if (k.reduce) {
+            // Add the work-groups' histogram rows to the outputs, which
+            // work-group 0 of the kernel cleared (or clear them: no tiles).
+            HistFinArgs F;
+            memset(&F, 0, sizeof(F));
+            F.part = p->hrows;
+            F.one.hist = A.hist;
+            F.one.sum = A.sum;
+            F.one.nrows = k.grid;
+            F.one.crows = hist_chunk_rows(k.bins);
+            F.nseg = 1;
+            F.nchunks = hist_chunks(k.grid, F.one.crows);
+            F.bins = k.bins;
+            HIP_TRY(A.ntiles > 0 ? launch_hist_merge(F, s) : launch_hist_zero(F, s));
+        }
     }
     return SKEL_OK;
 }
@@ -256,6 +266,14 @@ skel_status ensure_resources(skel_plan p) {
         HIP_TRY(hipMalloc(&p->partials, sizeof(float) * g));
         HIP_TRY(hipMalloc(&p->ticket, 256));
         HIP_TRY(hipMemset(p->ticket, 0, 256));
+    }
+    if (p->lin.dom == DOM_U8 && p->lin.red >= 0 && !p->hrows) {
+        for (const Kernel& k : p->kernels)
+            if (k.reduce) {
+                const size_t words = 4 * (size_t)k.bins;
+                const size_t rows = std::max(1, k.grid);
+                HIP_TRY(hipMalloc(&p->hrows, sizeof(uint32_t) * words * rows));
+            }
     }
     if (p->lin.dom == DOM_NBODY && p->cfg.fusion == SKEL_FUSE_OFF && !p->nb_acc)
         HIP_TRY(hipMalloc(&p->nb_acc, sizeof(float4) * std::max<int64_t>(p->sh.N, 1)));
@@ -457,6 +475,10 @@ skel_status skel_plan_destroy(skel_plan p) {
     for (void* q : p->scratch)
         if (q) hipFree(q);
     if (p->partials) hipFree(p->partials);
+    if (p->hrows) hipFree(p->hrows);
+    if (p->d_segs) hipFree(p->d_segs);
+    if (p->h_segs) hipHostFree(p->h_segs);
+    if (p->b_rows) hipFree(p->b_rows);
     if (p->ticket) hipFree(p->ticket);
     if (p->nb_acc) hipFree(p->nb_acc);
     if (p->gexec) hipGraphExecDestroy(p->gexec);

@@ -2,8 +2,10 @@
 // content and size (the batch model of Sec. 2) run as one persistent kernel.
 // The host lays out a work list of wavefront tiles, largest requests first
 // (longest-processing-time order, so the tail of the launch is made of small
-// tiles), and captures [zero outputs, reset ticket, persistent kernel] into a
-// HIP graph that is replayed while the same buffers and shapes come back.
+// tiles), and captures [reset ticket, clear outputs, persistent kernel,
+// histogram merge] into a HIP graph that is replayed while the same buffers
+// and shapes come back.  Every tile stores its histogram as a row; the merge
+// sums each request's rows in chunks and adds them to its outputs.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -104,20 +106,27 @@ extern "C" skel_status skel_batch_run(skel_plan p, const skel_buffer* args, int3
         const skel_buffer* b = args + (size_t)y * nargs;
         return a[0].shape[0] * a[0].shape[1] > b[0].shape[0] * b[0].shape[1];
     });
+    // Queued replays of the previous graph may still read the work list and
+    // the histogram rows: wait for them before anything is rewritten.
+    HIP_TRY(hipStreamSynchronize(s));
     if ((size_t)nreq > p->d_reqs_cap) {
-        // The previous work list may still be in use by queued replays.
-        HIP_TRY(hipStreamSynchronize(s));
         if (p->d_reqs) hipFree(p->d_reqs);
         if (p->h_reqs) hipHostFree(p->h_reqs);
+        if (p->d_segs) hipFree(p->d_segs);
+        if (p->h_segs) hipHostFree(p->h_segs);
         p->d_reqs = nullptr;
         p->h_reqs = nullptr;
+        p->d_segs = nullptr;
+        p->h_segs = nullptr;
         p->d_reqs_cap = 0;
         HIP_TRY(hipMalloc(&p->d_reqs, sizeof(BatchReq) * nreq));
         HIP_TRY(hipHostMalloc((void**)&p->h_reqs, sizeof(BatchReq) * nreq, hipHostMallocDefault));
+        HIP_TRY(hipMalloc(&p->d_segs, sizeof(HistSeg) * nreq));
+        HIP_TRY(hipHostMalloc((void**)&p->h_segs, sizeof(HistSeg) * nreq, hipHostMallocDefault));
         p->d_reqs_cap = nreq;
     }
     if (!p->d_counter) HIP_TRY(hipMalloc(&p->d_counter, 256));
-    int64_t tiles = 0;
+    int64_t tiles = 0, chunks = 0;
     for (int k = 0; k < nreq; ++k) {
         const skel_buffer* a = args + (size_t)order[k] * nargs;
         BatchReq& R = p->h_reqs[k];
@@ -131,11 +140,29 @@ extern "C" skel_status skel_batch_run(skel_plan p, const skel_buffer* args, int3
         R.nbands = (R.W + bw - 1) / bw;
         R.nchunks = (R.H + tile_h - 1) / tile_h;
         R.tile_begin = (int32_t)tiles;
-        if (R.W > 0 && R.H > 0) tiles += (int64_t)R.nbands * R.nchunks;
+        const int64_t nt = (R.W > 0 && R.H > 0) ? (int64_t)R.nbands * R.nchunks : 0;
+        tiles += nt;
         if (tiles >= ((int64_t)1 << 31)) return set_error(SKEL_EUNSUPPORTED, "batch has too many tiles");
+        HistSeg& G = p->h_segs[k];
+        memset(&G, 0, sizeof(G));
+        G.hist = R.hist;
+        G.sum = R.sum;
+        G.row_begin = R.tile_begin;
+        G.nrows = (int32_t)nt;
+        G.crows = hist_chunk_rows(K.bins);
+        G.chunk_begin = (int32_t)chunks;
+        chunks += hist_chunks((int)nt, G.crows);
     }
-    HIP_TRY(hipStreamSynchronize(s));
+    const size_t words = 4 * (size_t)K.bins;
+    if (red >= 0 && (size_t)tiles * words > p->b_rows_cap) {
+        if (p->b_rows) hipFree(p->b_rows);
+        p->b_rows = nullptr;
+        p->b_rows_cap = 0;
+        HIP_TRY(hipMalloc(&p->b_rows, sizeof(uint32_t) * tiles * words));
+        p->b_rows_cap = (size_t)tiles * words;
+    }
     HIP_TRY(hipMemcpy(p->d_reqs, p->h_reqs, sizeof(BatchReq) * nreq, hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(p->d_segs, p->h_segs, sizeof(HistSeg) * nreq, hipMemcpyHostToDevice));
 
     BatchArgs A;
     memset(&A, 0, sizeof(A));
@@ -148,6 +175,8 @@ extern "C" skel_status skel_batch_run(skel_plan p, const skel_buffer* args, int3
     A.out_flip = K.img.out_flip;
     A.has_hist = red >= 0;
     A.hist_ks = hist_copies_log2(K.bins, kHistWaveWords);
+    A.bins = K.bins;
+    A.part = p->b_rows;
     A.counter = p->d_counter;
     A.pre = K.img.pre;
     A.post = K.img.post;
@@ -168,9 +197,17 @@ extern "C" skel_status skel_batch_run(skel_plan p, const skel_buffer* args, int3
     if (!p->cap_stream) HIP_TRY(hipStreamCreateWithFlags(&p->cap_stream, hipStreamNonBlocking));
     HIP_TRY(hipStreamBeginCapture(p->cap_stream, hipStreamCaptureModeThreadLocal));
     const char* kname = nullptr;
-    hipError_t e1 = red >= 0 ? launch_batch_zero(p->d_reqs, nreq, p->cap_stream) : hipSuccess;
-    hipError_t e2 = launch_fill_u32(p->d_counter, 1, 0, p->cap_stream);
-    hipError_t e3 = tiles > 0 ? launch_img_batch(A, grid, wg, p->cap_stream, &kname) : hipSuccess;
+    HistFinArgs F;
+    memset(&F, 0, sizeof(F));
+    F.part = p->b_rows;
+    F.segs = p->d_segs;
+    F.nseg = nreq;
+    F.nchunks = (int32_t)chunks;
+    F.bins = K.bins;
+    hipError_t e1 = launch_fill_u32(p->d_counter, 1, 0, p->cap_stream);
+    if (e1 == hipSuccess && red >= 0) e1 = launch_hist_zero(F, p->cap_stream);
+    hipError_t e2 = tiles > 0 ? launch_img_batch(A, grid, wg, p->cap_stream, &kname) : hipSuccess;
+    hipError_t e3 = red >= 0 ? launch_hist_merge(F, p->cap_stream) : hipSuccess;
     hipGraph_t g = nullptr;
     hipError_t e4 = hipStreamEndCapture(p->cap_stream, &g);
     if (e1 || e2 || e3 || e4) {

@@ -120,6 +120,7 @@ struct skel_plan_s {
     void* scratch[2] = {nullptr, nullptr};
     float* partials = nullptr;
     uint32_t* ticket = nullptr;
+    uint32_t* hrows = nullptr;      // image reduce: histogram rows, one per work-group
     float4* nb_acc = nullptr;
     // N-body loop graph
     hipStream_t cap_stream = nullptr;
@@ -130,6 +131,10 @@ struct skel_plan_s {
     size_t d_reqs_cap = 0;
     uint32_t* d_counter = nullptr;
     skel::BatchReq* h_reqs = nullptr;   // pinned host mirror of the work list
+    skel::HistSeg* d_segs = nullptr;    // per-request histogram segments
+    skel::HistSeg* h_segs = nullptr;
+    uint32_t* b_rows = nullptr;         // per-tile histogram rows
+    size_t b_rows_cap = 0;              // in words
     hipGraphExec_t bexec = nullptr;
     std::vector<int64_t> bkey;
     int batch_grid = 0;

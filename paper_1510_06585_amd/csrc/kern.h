@@ -29,8 +29,10 @@ struct OpList {
 struct ImgGroupArgs {
     const uint8_t* in;
     uint8_t* out;
-    uint32_t* hist;      // [4][256] or null
-    uint64_t* sum;       // [4] or null
+    uint32_t* part;      // histogram epilogue: one row of 4 x bins counts per work-group
+    uint32_t* hist;      // reduce outputs cleared by work-group 0 (may be null)
+    uint64_t* sum;
+    int32_t bins;        // values emitted are < bins (128 or 256)
     int32_t W, H;
     int32_t tile_h;      // rows per tile
     int32_t nbands;      // tiles across a row
@@ -66,6 +68,35 @@ const char* img_kernel_name(const ImgGroupArgs& a, bool blur, bool hist, int var
 // when the occupancy query is unavailable, e.g. without a device).
 int img_waves_per_cu(const ImgGroupArgs& a, bool blur, bool hist, int wg, int variant);
 
+// Merge of histogram rows (the reduce's merge function, Sec. 3.4): a segment
+// owns rows [row_begin, row_begin + nrows) of 4 x bins counts, summed in
+// chunks of crows rows by one 1024-thread work-group each, which adds its
+// non-zero counts (and the channel sums they imply) to the segment's
+// [4][256] histogram (may be null) and [4] sums with device-scope atomics.
+// The outputs must be cleared before (hist_zero, or work-group 0 of the image
+// kernel that writes the rows).
+struct HistSeg {
+    uint32_t* hist;
+    uint64_t* sum;
+    int32_t row_begin, nrows;
+    int32_t crows, chunk_begin;
+};
+struct HistFinArgs {
+    const uint32_t* part;
+    const HistSeg* segs;   // device array of nseg segments, or null for `one`
+    HistSeg one;
+    int32_t nseg;
+    int32_t nchunks;       // chunks over all segments
+    int32_t bins;
+    int32_t pad;
+};
+// Rows per chunk for rows of 4 x bins words: 8 rows per thread of a
+// 1024-thread work-group.
+int hist_chunk_rows(int bins);
+inline int hist_chunks(int n, int crows) { return n > 0 ? (n + crows - 1) / crows : 0; }
+hipError_t launch_hist_merge(const HistFinArgs& a, hipStream_t s);
+hipError_t launch_hist_zero(const HistFinArgs& a, hipStream_t s);
+
 // Work list entry of the batched persistent kernel (one per request).
 struct BatchReq {
     const uint8_t* in;
@@ -86,11 +117,13 @@ struct BatchArgs {
     int32_t in_flip, out_flip;
     int32_t has_hist;
     int32_t hist_ks;     // log2 copies per bin of the per-wavefront histograms
+    int32_t bins;        // values emitted are < bins
+    int32_t pad;
+    uint32_t* part;      // histogram rows, one per tile (global tile index)
     uint32_t* counter;   // work-queue ticket counter (zeroed before launch)
     OpList pre, post;
 };
 hipError_t launch_img_batch(const BatchArgs& a, int grid, int wg, hipStream_t s, const char** kname);
-hipError_t launch_batch_zero(const BatchReq* reqs, int nreq, hipStream_t s);
 // Resident work-groups per CU of the persistent kernel for this chain.
 int img_batch_blocks_per_cu(const BatchArgs& a, int wg);
 

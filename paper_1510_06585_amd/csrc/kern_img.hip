@@ -23,16 +23,6 @@
 
 namespace skel {
 
-// MurmurHash3 32-bit finaliser, written from its public description.
-static __device__ __forceinline__ uint32_t fmix32(uint32_t h) {
-    h ^= h >> 16;
-    h *= 0x85EBCA6Bu;
-    h ^= h >> 13;
-    h *= 0xC2B2AE35u;
-    h ^= h >> 16;
-    return h;
-}
-
 // Noise on one u16 pair: b = two hash bytes; r = b mod 33 computed as
 // b - 33 * ((b * 249) >> 13), exact for b in [0, 255]; out = clamp(v + r - 16).
 static __device__ __forceinline__ uint32_t noise_half(uint32_t v, uint32_t hb) {
@@ -69,8 +59,18 @@ static __device__ __forceinline__ uint32_t odd_bytes(uint32_t v) {
     return __builtin_amdgcn_perm(0u, v, 0x0C030C01u);
 }
 
+// The MurmurHash3 32-bit finaliser (written from its public description) of
+// the key seed ^ ((y << 16) | x), x < 2^16.  The key's high half does not
+// depend on x, so the finaliser's first xor-shift k ^ (k >> 16) equals
+// (S ^ (S >> 16)) ^ x with S = seed ^ (y << 16), a wavefront-uniform value.
 static __device__ __forceinline__ uint32_t px_hash(uint32_t seed, uint32_t x, uint32_t y) {
-    return fmix32(seed ^ ((y << 16) | x));
+    const uint32_t S = seed ^ (y << 16);
+    uint32_t h = (S ^ (S >> 16)) ^ x;
+    h *= 0x85EBCA6Bu;
+    h ^= h >> 13;
+    h *= 0xC2B2AE35u;
+    h ^= h >> 16;
+    return h;
 }
 
 static __device__ __forceinline__ void noise_px(uint32_t& e, uint32_t& o, uint32_t seed, uint32_t x,
@@ -174,6 +174,7 @@ static __device__ __forceinline__ int clampi(int v, int lo, int hi) { return v <
 
 // Input rows in flight per wavefront ahead of the row being computed.
 constexpr int kPrefetch = 4;
+static_assert(kPrefetch == 4, "row groups are written out for four slots (the blur ring length)");
 
 // Histogram modes: none, one privatised histogram per work-group, one per
 // wavefront (persistent batched kernel).  Per channel a work-group histogram
@@ -331,24 +332,34 @@ static __device__ __forceinline__ void band_tile(const ImgView& V, const OpList&
         };
 
         if constexpr (!BLUR) {
-            // Rows are prefetched kPrefetch ahead; slot k of the unrolled loop
-            // is refilled as soon as it is consumed (the refill index is
-            // clamped to the tile, so the last rows re-read cached lines).
+            // Rows are prefetched kPrefetch ahead; slot k is refilled as soon
+            // as it is consumed (refills are clamped to the tile, so the last
+            // rows re-read cached lines).  Whole groups of kPrefetch rows run
+            // in a loop with no early exit and the last y1 - y0 mod kPrefetch
+            // rows after it, so the loop back-edge only waits for the oldest
+            // row in flight.
             u32x4 nxt[kPrefetch];
 #pragma unroll
             for (int d = 0; d < kPrefetch; ++d) nxt[d] = load_row(min(y0 + d, y1 - 1));
-            for (int y = y0; y < y1; y += kPrefetch) {
-#pragma unroll
-                for (int k = 0; k < kPrefetch; ++k) {
-                    const int yy = y + k;
-                    if (yy >= y1) break;
-                    Px4 p;
-                    unpack(nxt[k], p);                               // slot consumed ...
-                    nxt[k] = load_row(min(yy + kPrefetch, y1 - 1));  // ... and refilled in place
-                    apply_ops<PRE>(pre, p, xc, yy, W);
-                    emit(p, yy);
-                }
+            auto row = [&](auto kc, int yy, bool refill) {
+                constexpr int k = decltype(kc)::value;
+                Px4 p;
+                unpack(nxt[k], p);                                              // slot consumed ...
+                if (refill) nxt[k] = load_row(min(yy + kPrefetch, y1 - 1));     // ... and refilled
+                apply_ops<PRE>(pre, p, xc, yy, W);
+                emit(p, yy);
+            };
+            int y = y0;
+            for (; y + kPrefetch <= y1; y += kPrefetch) {
+                row(std::integral_constant<int, 0>{}, y, true);
+                row(std::integral_constant<int, 1>{}, y + 1, true);
+                row(std::integral_constant<int, 2>{}, y + 2, true);
+                row(std::integral_constant<int, 3>{}, y + 3, true);
             }
+            const int rem = y1 - y;
+            if (rem > 0) row(std::integral_constant<int, 0>{}, y, false);
+            if (rem > 1) row(std::integral_constant<int, 1>{}, y + 1, false);
+            if (rem > 2) row(std::integral_constant<int, 2>{}, y + 2, false);
         } else {
             // Sliding 5-row window of horizontal sums: ring[s] holds the row
             // that leaves the window next time slot s is visited.
@@ -369,41 +380,49 @@ static __device__ __forceinline__ void band_tile(const ImgView& V, const OpList&
                 }
             }
             // Input rows y+2 ... are prefetched kPrefetch ahead (kPrefetch
-            // divides the unroll factor 4, so every slot index is a constant);
+            // equals the ring length, so every slot index is a constant);
             // refills are clamped to the last row the tile needs, y1 + 1.
+            // As above, whole groups of four rows loop with no early exit.
             const int last = min(y1 + 1, H - 1);
             u32x4 nxt[kPrefetch];
 #pragma unroll
             for (int d = 0; d < kPrefetch; ++d) nxt[d] = load_row(min(y0 + 2 + d, last));
-            for (int y = y0; y < y1; y += 4) {
+            auto row = [&](auto kc, int yy, bool refill) {
+                constexpr int k = decltype(kc)::value;
+                const int rr = min(yy + 2, H - 1);
+                Px4 p;
+                unpack(nxt[k], p);                                                // slot consumed ...
+                if (refill) nxt[k] = load_row(min(yy + 2 + kPrefetch, last));     // ... and refilled
+                apply_ops<PRE>(pre, p, xc, rr, W);
+                uint32_t hE[4], hO[4];
+                hsum5(p.e, hE);
+                hsum5(p.o, hO);
+                Px4 q;
 #pragma unroll
-                for (int k = 0; k < 4; ++k) {
-                    const int yy = y + k;
-                    if (yy >= y1) break;
-                    const int rr = min(yy + 2, H - 1);
-                    Px4 p;
-                    unpack(nxt[k % kPrefetch], p);                               // slot consumed ...
-                    nxt[k % kPrefetch] = load_row(min(yy + 2 + kPrefetch, last));  // ... refilled in place
-                    apply_ops<PRE>(pre, p, xc, rr, W);
-                    uint32_t hE[4], hO[4];
-                    hsum5(p.e, hE);
-                    hsum5(p.o, hO);
-                    Px4 q;
-#pragma unroll
-                    for (int i = 0; i < 4; ++i) {
-                        const uint32_t fe = VE[i] + hE[i];
-                        const uint32_t fo = VO[i] + hO[i];
-                        VE[i] = fe - ringE[k][i];
-                        VO[i] = fo - ringO[k][i];
-                        ringE[k][i] = hE[i];
-                        ringO[k][i] = hO[i];
-                        q.e[i] = div25_pair(fe);
-                        q.o[i] = div25_pair(fo);
-                    }
-                    apply_ops<POST>(post, q, xc, yy, W);
-                    emit(q, yy);
+                for (int i = 0; i < 4; ++i) {
+                    const uint32_t fe = VE[i] + hE[i];
+                    const uint32_t fo = VO[i] + hO[i];
+                    VE[i] = fe - ringE[k][i];
+                    VO[i] = fo - ringO[k][i];
+                    ringE[k][i] = hE[i];
+                    ringO[k][i] = hO[i];
+                    q.e[i] = div25_pair(fe);
+                    q.o[i] = div25_pair(fo);
                 }
+                apply_ops<POST>(post, q, xc, yy, W);
+                emit(q, yy);
+            };
+            int y = y0;
+            for (; y + 4 <= y1; y += 4) {
+                row(std::integral_constant<int, 0>{}, y, true);
+                row(std::integral_constant<int, 1>{}, y + 1, true);
+                row(std::integral_constant<int, 2>{}, y + 2, true);
+                row(std::integral_constant<int, 3>{}, y + 3, true);
             }
+            const int rem = y1 - y;
+            if (rem > 0) row(std::integral_constant<int, 0>{}, y, false);
+            if (rem > 1) row(std::integral_constant<int, 1>{}, y + 1, false);
+            if (rem > 2) row(std::integral_constant<int, 2>{}, y + 2, false);
         }
     };
     if (interior)
@@ -412,54 +431,44 @@ static __device__ __forceinline__ void band_tile(const ImgView& V, const OpList&
         sweep(std::false_type{});
 }
 
-static __device__ __forceinline__ uint64_t wave_sum_u64(uint64_t v) {
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) {
-        const uint32_t lo = __shfl_xor((unsigned int)(v & 0xFFFFFFFFu), off, 64);
-        const uint32_t hi = __shfl_xor((unsigned int)(v >> 32), off, 64);
-        v += ((uint64_t)hi << 32) | lo;
-    }
-    return v;
-}
-
-// Merges a privatised LDS histogram into the global histogram and channel
-// sums by addition (the merge function of Sec. 3.4).  Counter (c, v, copy)
-// is at word c * CS + v * 2^hks + copy; the 2^hks copies of a bin are added
-// first.  `first`/`step` select the bins this thread handles; the lanes of a
-// wavefront cover disjoint bins.  Channel sums are derived from the counts.
+// Sums the 2^hks copies of every counter of a privatised LDS histogram and
+// stores the counts as one row of 4 x bins words (channel-major) with plain
+// stores; threads [first, first + step) cover the row.  The rows are merged by
+// the histogram finalise kernels, so no device-wide atomics are needed.
+// Counter (c, v, copy) is at word c * CS + v * 2^hks + copy; thread order
+// starts each bin's copy sum at a different copy to spread LDS banks.
 template <int CS>
-static __device__ __forceinline__ void flush_hist(const uint32_t* lh, int hks, uint32_t* hist, uint64_t* sum,
-                                                  int first, int step, int lane) {
+static __device__ __forceinline__ void write_hist_row(const uint32_t* lh, int hks, uint32_t* row, int first,
+                                                      int step) {
     const int copies = 1 << hks;
     const int bins = CS >> hks;
-    uint64_t s[4];
-#pragma unroll
-    for (int c = 0; c < 4; ++c) {
-        s[c] = 0;
-        for (int v = first; v < bins; v += step) {
-            const uint32_t* w = lh + c * CS + (v << hks);
-            uint32_t n = 0;
-            for (int j = 0; j < copies; ++j) n += w[(j + v) & (copies - 1)];
-            if (n) {
-                if (hist) atomicAdd(&hist[c * 256 + v], n);
-                s[c] += (uint64_t)v * n;
-            }
-        }
-    }
-#pragma unroll
-    for (int c = 0; c < 4; ++c) {
-        const uint64_t t = wave_sum_u64(s[c]);
-        if (lane == 0 && sum && t) atomicAdd((unsigned long long*)&sum[c], (unsigned long long)t);
+    for (int b = first; b < 4 * bins; b += step) {
+        const int c = b >> (__builtin_ctz((unsigned)bins));
+        const int v = b & (bins - 1);
+        const uint32_t* w = lh + c * CS + (v << hks);
+        uint32_t n = 0;
+        for (int j = 0; j < copies; ++j) n += w[(j + v) & (copies - 1)];
+        row[b] = n;
     }
 }
 
-template <int PRE, int POST, bool BLUR, bool HIST>
+// FL >= 0 fixes the mirror flags at compile time (bit 0: input, bit 1:
+// output), which removes the per-row selects of the flipped data order;
+// FL = -1 reads them from the arguments.
+template <int PRE, int POST, bool BLUR, bool HIST, int FL>
 __global__ void __launch_bounds__(256) img_band_kernel(const ImgGroupArgs A) {
     __shared__ uint32_t lh[HIST ? 4 * kHistWgChan : 1];
     const int lane = threadIdx.x & 63;
     const int nw = blockDim.x >> 6;
     const int wave = wave_uniform(threadIdx.x >> 6);
     if constexpr (HIST) {
+        // Work-group 0 clears the reduce outputs; the merge kernel that runs
+        // after this launch adds the work-groups' histogram rows to them.
+        if (blockIdx.x == 0) {
+            for (int b = threadIdx.x; b < 1024; b += blockDim.x)
+                if (A.hist) A.hist[b] = 0;
+            if (threadIdx.x < 4 && A.sum) A.sum[threadIdx.x] = 0;
+        }
         for (int b = threadIdx.x; b < 4 * kHistWgChan; b += blockDim.x) lh[b] = 0;
         __syncthreads();
     }
@@ -469,21 +478,23 @@ __global__ void __launch_bounds__(256) img_band_kernel(const ImgGroupArgs A) {
         const int chunk = tile / A.nbands;
         const int y0 = chunk * A.tile_h;
         const int y1 = min(y0 + A.tile_h, A.H);
-        const ImgView V{A.in, A.out, A.W, A.H, A.in_flip, A.out_flip, A.write_out};
+        const ImgView V{A.in, A.out, A.W, A.H, FL < 0 ? A.in_flip : (FL & 1), FL < 0 ? A.out_flip : (FL >> 1),
+                        A.write_out};
         band_tile<PRE, POST, BLUR, HIST ? HIST_WG : HIST_NONE>(V, A.pre, A.post, band, y0, y1, lane, lh,
                                                                 A.hist_ks);
     }
     if constexpr (HIST) {
         __syncthreads();
-        flush_hist<kHistWgChan>(lh, A.hist_ks, A.hist, A.sum, threadIdx.x, blockDim.x, lane);
+        write_hist_row<kHistWgChan>(lh, A.hist_ks, A.part + (size_t)blockIdx.x * 4 * A.bins, threadIdx.x,
+                                    blockDim.x);
     }
 }
 
 // Persistent batched kernel: every wavefront takes tiles from a global ticket
 // counter until the work list is exhausted, finds the owning request by binary
 // search over the requests' first tile indices, runs the fused chain on the
-// tile and merges its own LDS histogram into that request's outputs.
-template <int PRE, int POST, bool BLUR, bool HIST>
+// tile and stores its own LDS histogram as the tile's histogram row.
+template <int PRE, int POST, bool BLUR, bool HIST, int FL>
 __global__ void __launch_bounds__(256) img_batch_kernel(const BatchArgs A) {
     __shared__ uint32_t lh_all[HIST ? 4 * 4 * kHistWaveChan : 1];
     const int lane = threadIdx.x & 63;
@@ -510,26 +521,105 @@ __global__ void __launch_bounds__(256) img_batch_kernel(const BatchArgs A) {
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
             __builtin_amdgcn_wave_barrier();
         }
-        const ImgView V{R.in, R.out, R.W, R.H, A.in_flip, A.out_flip, 1};
+        const ImgView V{R.in, R.out, R.W, R.H, FL < 0 ? A.in_flip : (FL & 1), FL < 0 ? A.out_flip : (FL >> 1), 1};
         band_tile<PRE, POST, BLUR, HIST ? HIST_WAVE : HIST_NONE>(V, A.pre, A.post, band, y0, y1, lane, lh,
                                                                   A.hist_ks);
         if constexpr (HIST) {
             __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
             __builtin_amdgcn_wave_barrier();
-            flush_hist<kHistWaveChan>(lh, A.hist_ks, R.hist, R.sum, lane, 64, lane);
+            write_hist_row<kHistWaveChan>(lh, A.hist_ks, A.part + (size_t)t * 4 * A.bins, lane, 64);
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
             __builtin_amdgcn_wave_barrier();
         }
     }
 }
 
-// Zeroes every request's histogram and sums (one work-group per request).
-__global__ void batch_zero_kernel(const BatchReq* reqs, int nreq) {
-    const int r = blockIdx.x;
-    if (r >= nreq) return;
-    const BatchReq R = reqs[r];
+static __device__ __forceinline__ u32x4 ldg128(const uint32_t* p) { return *reinterpret_cast<const u32x4*>(p); }
+
+static __device__ __forceinline__ int seg_of(const HistFinArgs& F, int chunk) {
+    if (!F.segs) return 0;
+    int lo = 0, hi = F.nseg - 1;
+    while (lo < hi) {   // last segment with chunk_begin <= chunk
+        const int mid = (lo + hi + 1) >> 1;
+        if (F.segs[mid].chunk_begin <= chunk) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
+// Sum of rows [0, nrows) (stride `words`) of `base` by a 1024-thread work-
+// group: thread (g, q), g < G = 4096 / words, sums the 16-byte word group q of
+// rows g, g + G, ... with kSumUnroll loads in flight, and the G partial sums
+// of q meet in LDS.  Threads with g == 0 return the total of their q.
+constexpr int kFinThreads = 1024;
+constexpr int kSumUnroll = 8;
+static __device__ __forceinline__ u32x4 sum_rows(const uint32_t* base, int nrows, int words, u32x4* red) {
+    const int nq = words >> 2;
+    const int G = kFinThreads / nq;
+    const int q = threadIdx.x % nq, g = threadIdx.x / nq;
+    u32x4 acc[kSumUnroll];
+#pragma unroll
+    for (int u = 0; u < kSumUnroll; ++u) acc[u] = u32x4{0, 0, 0, 0};
+    for (int r0 = g; r0 < nrows; r0 += kSumUnroll * G) {
+        u32x4 v[kSumUnroll];
+#pragma unroll
+        for (int u = 0; u < kSumUnroll; ++u) {
+            const int r = r0 + u * G;
+            v[u] = r < nrows ? ldg128(base + (size_t)r * words + 4 * q) : u32x4{0, 0, 0, 0};
+        }
+#pragma unroll
+        for (int u = 0; u < kSumUnroll; ++u) acc[u] += v[u];
+    }
+#pragma unroll
+    for (int u = 1; u < kSumUnroll; ++u) acc[0] += acc[u];
+    __syncthreads();   // red may still be read by a previous call
+    red[threadIdx.x] = acc[0];
+    __syncthreads();
+    u32x4 t = u32x4{0, 0, 0, 0};
+    if (g == 0)
+        for (int k = 0; k < G; ++k) t += red[k * nq + q];
+    return t;
+}
+
+// Merge (one launch after the kernels that wrote the rows): work-group k sums
+// the rows of chunk k and adds the non-zero counts, and the channel sums they
+// imply, to its segment's outputs with device-scope atomics.  The outputs
+// were cleared before the rows were written (by hist_zero_kernel or by the
+// image kernel itself), so about (bins + 4) atomics per chunk remain.
+__global__ void __launch_bounds__(kFinThreads) hist_merge_kernel(const HistFinArgs F) {
+    __shared__ u32x4 red[kFinThreads];
+    __shared__ unsigned long long csum[4];
+    const int k = blockIdx.x;
+    const HistSeg& S = F.segs ? F.segs[seg_of(F, k)] : F.one;
+    const int words = 4 * F.bins;
+    const int r0 = S.row_begin + (k - S.chunk_begin) * S.crows;
+    const int r1 = min(r0 + S.crows, S.row_begin + S.nrows);
+    if (threadIdx.x < 4) csum[threadIdx.x] = 0;
+    const u32x4 n = sum_rows(F.part + (size_t)r0 * words, max(r1 - r0, 0), words, red);
+    if ((int)threadIdx.x < (words >> 2)) {
+        const int b = 4 * threadIdx.x;
+        const int c = b >> __builtin_ctz((unsigned)F.bins), v = b & (F.bins - 1);
+        if (S.hist) {
+            uint32_t* h = S.hist + c * 256 + v;
+            if (n.x) atomicAdd(h, n.x);
+            if (n.y) atomicAdd(h + 1, n.y);
+            if (n.z) atomicAdd(h + 2, n.z);
+            if (n.w) atomicAdd(h + 3, n.w);
+        }
+        const unsigned long long t = (unsigned long long)v * n.x + (unsigned long long)(v + 1) * n.y +
+                                     (unsigned long long)(v + 2) * n.z + (unsigned long long)(v + 3) * n.w;
+        if (t) atomicAdd(&csum[c], t);
+    }
+    __syncthreads();
+    if (threadIdx.x < 4 && S.sum && csum[threadIdx.x])
+        atomicAdd((unsigned long long*)&S.sum[threadIdx.x], csum[threadIdx.x]);
+}
+
+// Clears the histogram and sums of every segment (one work-group each).
+__global__ void hist_zero_kernel(const HistFinArgs F) {
+    const HistSeg& S = F.segs ? F.segs[blockIdx.x] : F.one;
     for (int b = threadIdx.x; b < 1024; b += blockDim.x)
-        if (R.hist) R.hist[b] = 0;
-    if (threadIdx.x < 4 && R.sum) R.sum[threadIdx.x] = 0;
+        if (S.hist) S.hist[b] = 0;
+    if (threadIdx.x < 4 && S.sum) S.sum[threadIdx.x] = 0;
 }
 
 __global__ void fill_u32_kernel(uint32_t* p, uint64_t n, uint32_t v) {
@@ -561,40 +651,51 @@ typedef void (*batch_kfn)(const BatchArgs);
 struct ImgEntry {
     int pre, post;
     bool blur, hist;
+    int fl;   // compile-time mirror flags, -1 = from the arguments
     img_kfn fn;
     batch_kfn bfn;
     const char* name;
 };
 
-#define SKEL_IMG_ENTRY(P, Q, B, Hh, NAME) \
-    {P, Q, B, Hh, img_band_kernel<P, Q, B, Hh>, img_batch_kernel<P, Q, B, Hh>, NAME}
+#define SKEL_IMG_ENTRY(P, Q, B, Hh, FL, NAME) \
+    {P, Q, B, Hh, FL, img_band_kernel<P, Q, B, Hh, FL>, img_batch_kernel<P, Q, B, Hh, FL>, NAME}
+// Without a stencil the input is never mirrored (mirrors fold into the
+// output address), so those chains need FL 0 and 2 only.
+#define SKEL_IMG_POINT(P, Hh, NAME) SKEL_IMG_ENTRY(P, 0, false, Hh, 0, NAME), SKEL_IMG_ENTRY(P, 0, false, Hh, 2, NAME)
+#define SKEL_IMG_STENCIL(P, Hh, NAME)                                           \
+    SKEL_IMG_ENTRY(P, 0, true, Hh, 0, NAME), SKEL_IMG_ENTRY(P, 0, true, Hh, 2, NAME), \
+        SKEL_IMG_ENTRY(P, 0, true, Hh, -1, NAME)
 
 // Specialised chains: 1 = noise, 2 = solarise, 9 = noise then solarise.
 static const ImgEntry kImgTable[] = {
-    SKEL_IMG_ENTRY(0, 0, false, false, "img_copy"),
-    SKEL_IMG_ENTRY(1, 0, false, false, "img_noise"),
-    SKEL_IMG_ENTRY(2, 0, false, false, "img_solarise"),
-    SKEL_IMG_ENTRY(0, 0, false, true, "img_reduce"),
-    SKEL_IMG_ENTRY(0, 0, true, false, "img_blur"),
-    SKEL_IMG_ENTRY(0, 0, true, true, "img_blur_reduce"),
-    SKEL_IMG_ENTRY(9, 0, false, false, "img_noise_sol"),
-    SKEL_IMG_ENTRY(9, 0, false, true, "img_noise_sol_reduce"),
-    SKEL_IMG_ENTRY(9, 0, true, false, "img_noise_sol_blur"),
-    SKEL_IMG_ENTRY(9, 0, true, true, "img_noise_sol_blur_reduce"),
-    SKEL_IMG_ENTRY(kGeneric, kGeneric, false, false, "img_generic"),
-    SKEL_IMG_ENTRY(kGeneric, kGeneric, false, true, "img_generic_reduce"),
-    SKEL_IMG_ENTRY(kGeneric, kGeneric, true, false, "img_generic_blur"),
-    SKEL_IMG_ENTRY(kGeneric, kGeneric, true, true, "img_generic_blur_reduce"),
+    SKEL_IMG_POINT(0, false, "img_copy"),
+    SKEL_IMG_POINT(1, false, "img_noise"),
+    SKEL_IMG_POINT(2, false, "img_solarise"),
+    SKEL_IMG_POINT(0, true, "img_reduce"),
+    SKEL_IMG_POINT(9, false, "img_noise_sol"),
+    SKEL_IMG_POINT(9, true, "img_noise_sol_reduce"),
+    SKEL_IMG_STENCIL(0, false, "img_blur"),
+    SKEL_IMG_STENCIL(0, true, "img_blur_reduce"),
+    SKEL_IMG_STENCIL(9, false, "img_noise_sol_blur"),
+    SKEL_IMG_STENCIL(9, true, "img_noise_sol_blur_reduce"),
+    SKEL_IMG_ENTRY(kGeneric, kGeneric, false, false, -1, "img_generic"),
+    SKEL_IMG_ENTRY(kGeneric, kGeneric, false, true, -1, "img_generic_reduce"),
+    SKEL_IMG_ENTRY(kGeneric, kGeneric, true, false, -1, "img_generic_blur"),
+    SKEL_IMG_ENTRY(kGeneric, kGeneric, true, true, -1, "img_generic_blur_reduce"),
 };
 
-static const ImgEntry* find_entry(const OpList& pre, const OpList& post, bool blur, bool hist, int variant) {
+static const ImgEntry* find_entry(const OpList& pre, const OpList& post, bool blur, bool hist, int in_flip,
+                                  int out_flip, int variant) {
     const int pe = encode_ops(pre), qe = encode_ops(post);
+    const int fl = (in_flip ? 1 : 0) | (out_flip ? 2 : 0);
     const int n = (int)(sizeof(kImgTable) / sizeof(kImgTable[0]));
     if (variant == 0 && pre.n <= 6 && post.n <= 6) {
-        for (int i = 0; i < n; ++i) {
-            const ImgEntry& e = kImgTable[i];
-            if (e.pre == pe && e.post == qe && e.blur == blur && e.hist == hist) return &e;
-        }
+        for (int pass = 0; pass < 2; ++pass)
+            for (int i = 0; i < n; ++i) {
+                const ImgEntry& e = kImgTable[i];
+                if (e.pre == pe && e.post == qe && e.blur == blur && e.hist == hist && e.fl == (pass ? -1 : fl))
+                    return &e;
+            }
     }
     for (int i = 0; i < n; ++i) {
         const ImgEntry& e = kImgTable[i];
@@ -604,7 +705,7 @@ static const ImgEntry* find_entry(const OpList& pre, const OpList& post, bool bl
 }
 
 int img_waves_per_cu(const ImgGroupArgs& a, bool blur, bool hist, int wg, int variant) {
-    const ImgEntry* e = find_entry(a.pre, a.post, blur, hist, variant);
+    const ImgEntry* e = find_entry(a.pre, a.post, blur, hist, a.in_flip, a.out_flip, variant);
     int nb = 0;
     if (!e || hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, reinterpret_cast<const void*>(e->fn), wg, 0) !=
                   hipSuccess ||
@@ -616,13 +717,13 @@ int img_waves_per_cu(const ImgGroupArgs& a, bool blur, bool hist, int wg, int va
 }
 
 const char* img_kernel_name(const ImgGroupArgs& a, bool blur, bool hist, int variant) {
-    const ImgEntry* e = find_entry(a.pre, a.post, blur, hist, variant);
+    const ImgEntry* e = find_entry(a.pre, a.post, blur, hist, a.in_flip, a.out_flip, variant);
     return e ? e->name : "";
 }
 
 hipError_t launch_img_group(const ImgGroupArgs& a, bool blur, bool hist, int wg, int variant, hipStream_t s,
                             const char** kname) {
-    const ImgEntry* e = find_entry(a.pre, a.post, blur, hist, variant);
+    const ImgEntry* e = find_entry(a.pre, a.post, blur, hist, a.in_flip, a.out_flip, variant);
     if (!e) return hipErrorInvalidValue;
     if (kname) *kname = e->name;
     if (a.ntiles <= 0) return hipSuccess;
@@ -633,7 +734,7 @@ hipError_t launch_img_group(const ImgGroupArgs& a, bool blur, bool hist, int wg,
 }
 
 hipError_t launch_img_batch(const BatchArgs& a, int grid, int wg, hipStream_t s, const char** kname) {
-    const ImgEntry* e = find_entry(a.pre, a.post, a.has_blur != 0, a.has_hist != 0, 0);
+    const ImgEntry* e = find_entry(a.pre, a.post, a.has_blur != 0, a.has_hist != 0, a.in_flip, a.out_flip, 0);
     if (!e) return hipErrorInvalidValue;
     if (kname) *kname = e->name;
     if (wg != 256 && wg != 128 && wg != 64) return hipErrorInvalidValue;
@@ -641,14 +742,23 @@ hipError_t launch_img_batch(const BatchArgs& a, int grid, int wg, hipStream_t s,
     return hipGetLastError();
 }
 
-hipError_t launch_batch_zero(const BatchReq* reqs, int nreq, hipStream_t s) {
-    if (nreq <= 0) return hipSuccess;
-    hipLaunchKernelGGL(batch_zero_kernel, dim3(nreq), dim3(256), 0, s, reqs, nreq);
+int hist_chunk_rows(int bins) { return kSumUnroll * (kFinThreads / bins); }
+
+hipError_t launch_hist_merge(const HistFinArgs& a, hipStream_t s) {
+    if (a.bins != 128 && a.bins != 256) return hipErrorInvalidValue;
+    if (a.nchunks <= 0) return hipSuccess;
+    hipLaunchKernelGGL(hist_merge_kernel, dim3(a.nchunks), dim3(kFinThreads), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_hist_zero(const HistFinArgs& a, hipStream_t s) {
+    if (a.nseg <= 0) return hipSuccess;
+    hipLaunchKernelGGL(hist_zero_kernel, dim3(a.nseg), dim3(256), 0, s, a);
     return hipGetLastError();
 }
 
 int img_batch_blocks_per_cu(const BatchArgs& a, int wg) {
-    const ImgEntry* e = find_entry(a.pre, a.post, a.has_blur != 0, a.has_hist != 0, 0);
+    const ImgEntry* e = find_entry(a.pre, a.post, a.has_blur != 0, a.has_hist != 0, a.in_flip, a.out_flip, 0);
     if (!e) return 0;
     int nb = 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, reinterpret_cast<const void*>(e->bfn), wg, 0) != hipSuccess)

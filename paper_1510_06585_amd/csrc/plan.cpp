@@ -375,14 +375,17 @@ int device_cu_count() {
     return cus;
 }
 
-// Rows per tile such that one launch is a single round of resident
-// wavefronts: a grid larger than the resident capacity leaves a tail round of
-// a few wavefronts that runs alone.  Stencil tiles keep at least 16 rows (the
-// two halo rows above and below are recomputed per tile).
+// Rows per tile for `rounds` rounds of resident wavefronts.  The waves that
+// share a SIMD do not progress evenly (the oldest issues first), so with a
+// single round the last wave of each SIMD runs alone at the end; several
+// rounds of shorter tiles keep the SIMDs occupied until the tail, which is
+// one short tile.  Stencil tiles recompute two halo rows above and below, so
+// they take 2 rounds and at least 16 rows; other tiles take 4 rounds.
 static int fitted_tile_h(const ImgGroupArgs& A, bool blur, bool hist, const Config& c) {
     if (A.W <= 0 || A.H <= 0) return 1;
+    const int rounds = blur ? 2 : 4;
     const int64_t resident = (int64_t)img_waves_per_cu(A, blur, hist, c.wg, c.variant) * device_cu_count();
-    const int64_t chunks = std::max<int64_t>(1, resident / std::max<int32_t>(1, A.nbands));
+    const int64_t chunks = std::max<int64_t>(1, rounds * resident / std::max<int32_t>(1, A.nbands));
     int th = (int)((A.H + chunks - 1) / chunks);
     th = std::max(th, blur ? 16 : 4);
     return std::min(th, (int)A.H);
@@ -454,6 +457,7 @@ skel_status build_kernels(const Linear& L, const Shape& sh, const Config& c, std
             A.ntiles = (sh.W == 0 || sh.H == 0) ? 0 : (int32_t)(A.nbands * chunks);
             A.write_out = 1;
             A.hist_ks = hist_copies_log2(bins, kHistWgWords);
+            A.bins = bins;
             K.bins = bins;
             K.grid = (A.ntiles + c.wg / 64 - 1) / (c.wg / 64);
             K.name = img_kernel_name(A, K.blur, K.reduce, c.variant);
@@ -500,6 +504,8 @@ skel_status build_kernels(const Linear& L, const Shape& sh, const Config& c, std
             A.ntiles = (sh.W == 0 || sh.H == 0) ? 0 : (int32_t)(A.nbands * chunks);
             A.write_out = 0;
             A.hist_ks = hist_copies_log2(bins, kHistWgWords);
+            A.bins = bins;
+            R.bins = bins;
             R.grid = (A.ntiles + c.wg / 64 - 1) / (c.wg / 64);
             R.name = img_kernel_name(A, false, true, c.variant);
         } else {

@@ -31,9 +31,9 @@ import json
 import os
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-FUSED = "img_band_kernel<9, 0, true, true>"
+FUSED = "img_band_kernel<9, 0, true, true, 2>"
 FUSED_NAME = "img_noise_sol_blur_reduce"
-COPY = "img_band_kernel<0, 0, false, false>"
+COPY = "img_band_kernel<0, 0, false, false, 0>"
 COPY_BYTES = 2 * 8192 * 8192 * 4
 COMMANDS = (
     "rocprofv3 --kernel-trace --stats -d DIR -o cfg2 --output-format csv -- python3 bench.py "
