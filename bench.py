@@ -189,8 +189,8 @@ def bench_config2(steps, warmup, do_cpu):
         "data": "synthetic",
         "config": {"workload": "fused Pipeline+MapReduce, 8192x8192 RGBA u8: noise>solarise>blur5x5>mirror, "
                                "256-bin per-channel histogram + u64 channel sums",
-                   "H": H, "W": W, "kernels": len(desc["kernels"]), "tile_h": desc["config"]["tile_h"],
-                   "wg": desc["config"]["wg"]},
+                   "H": H, "W": W, "kernels": len(desc["kernels"]), "tile_h": desc["kernels"][0].get("tile_h"),
+                   "wg": desc["kernels"][0].get("wg")},
         "roofline": {"bound": "hbm", "kernel": kname, "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": traffic, "kernel_ms": round(k_ms, 5), "algorithmic_bytes": int(algo)},
@@ -310,7 +310,8 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
-    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=500,
+                    help="untimed steps first; the GPU needs ~0.1 s of load to reach its working clocks")
     ap.add_argument("--no-extras", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--selector", action="store_true", help="run the learned-selector experiment instead")
@@ -320,8 +321,8 @@ def main():
     ap.add_argument("--selector-test", type=int, default=200)
     a = ap.parse_args()
     if a.gpus != 1:
-        print(f"bench.py measures one GPU only (asked for --gpus {a.gpus}); multi-GPU runs are not part "
-              f"of this build", file=sys.stderr)
+        print(f"bench.py measures one GPU only (asked for --gpus {a.gpus}); runs over several GPUs are "
+              f"not supported", file=sys.stderr)
         sys.exit(2)
     import torch
     import paper_1510_06585_amd as sk

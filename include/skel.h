@@ -278,6 +278,23 @@ skel_status skel_tune(skel_node root, const skel_buffer* args, int32_t nargs, co
                       int32_t reps, int32_t max_configs, uint64_t sample_seed, skel_plan_opts* best,
                       double* best_us);
 
+/* Profile building by Algorithm 1 (Sec. 3.2), on one GPU: the candidate set
+ * of skel_tune is walked as ordered dimensions with early stopping instead of
+ * exhaustively.  Fusion partitions go fewest kernels first, and the search
+ * ends at the first partition (after the first) that does not improve on the
+ * best time; per partition, work-group sizes go in non-increasing order of
+ * occupancy (resident wavefronts per CU; sizes below occ_threshold x the best
+ * occupancy are filtered out, 0 keeps all), and the first size that does not
+ * improve ends that partition; per size, the inner parameter (image tile
+ * height, fp32 vectors per thread, N-body j-slices) increases while each step
+ * improves by at least precision_us microseconds.  Every timed configuration
+ * is appended to db_path (may be NULL) in skel_tune's format; *timed (may be
+ * NULL) receives their number.  Timing, synchronisation and the overwriting
+ * of the arguments are as in skel_tune. */
+skel_status skel_tune_pruned(skel_node root, const skel_buffer* args, int32_t nargs, const char* db_path,
+                             int32_t reps, double precision_us, double occ_threshold, skel_plan_opts* best,
+                             double* best_us, int32_t* timed);
+
 /* Number of valid configurations skel_tune would time exhaustively for
  * (root, shapes), i.e. the cost model's candidate set. */
 skel_status skel_config_count(skel_node root, const skel_buffer* proto, int32_t nargs, int32_t* count);

@@ -180,7 +180,6 @@ skel_status run_vector(skel_plan p, const skel_buffer* args, hipStream_t s) {
         for (size_t j = 0; j < k.side_args.size(); ++j) A.side[j] = (const float*)args[k.side_args[j]].data;
         if (k.reduce && p->sh.n > 0) {
             A.partials = p->partials;
-            A.ticket = p->ticket;
             A.sum_out = sum_out;
         }
         const bool prof = (int)ki == p->prof_kernel;
@@ -264,8 +263,6 @@ skel_status ensure_resources(skel_plan p) {
         for (const Kernel& k : p->kernels)
             if (k.reduce) g = std::max(g, k.grid);
         HIP_TRY(hipMalloc(&p->partials, sizeof(float) * g));
-        HIP_TRY(hipMalloc(&p->ticket, 256));
-        HIP_TRY(hipMemset(p->ticket, 0, 256));
     }
     if (p->lin.dom == DOM_U8 && p->lin.red >= 0 && !p->hrows) {
         for (const Kernel& k : p->kernels)
@@ -479,7 +476,7 @@ skel_status skel_plan_destroy(skel_plan p) {
     if (p->d_segs) hipFree(p->d_segs);
     if (p->h_segs) hipHostFree(p->h_segs);
     if (p->b_rows) hipFree(p->b_rows);
-    if (p->ticket) hipFree(p->ticket);
+    if (p->d_tile_req) hipFree(p->d_tile_req);
     if (p->nb_acc) hipFree(p->nb_acc);
     if (p->gexec) hipGraphExecDestroy(p->gexec);
     if (p->bexec) hipGraphExecDestroy(p->bexec);

@@ -71,6 +71,7 @@ extern "C" skel_status skel_batch_run(skel_plan p, const skel_buffer* args, int3
         return set_error(SKEL_EUNSUPPORTED, "batched runs need a fully fused image plan (one kernel)");
     if (nargs != (int32_t)p->proto.size()) return set_error(SKEL_EINVAL, "expected %d arguments per request", (int)p->proto.size());
     if (nreq < 0 || (nreq > 0 && !args)) return set_error(SKEL_EINVAL, "bad request array");
+    if (nreq > 65535) return set_error(SKEL_EUNSUPPORTED, "at most 65535 requests per batch");
     const Kernel& K = p->kernels[0];
     const int red = p->lin.red;
     const bool inplace_ok = !(K.blur || K.img.in_flip || K.img.out_flip);
@@ -161,12 +162,28 @@ extern "C" skel_status skel_batch_run(skel_plan p, const skel_buffer* args, int3
         HIP_TRY(hipMalloc(&p->b_rows, sizeof(uint32_t) * tiles * words));
         p->b_rows_cap = (size_t)tiles * words;
     }
+    // Tile -> request table (tiles are numbered request by request).
+    std::vector<uint16_t> tile_req((size_t)tiles);
+    for (int k = 0; k < nreq; ++k) {
+        const int64_t end = k + 1 < nreq ? p->h_reqs[k + 1].tile_begin : tiles;
+        for (int64_t t = p->h_reqs[k].tile_begin; t < end; ++t) tile_req[(size_t)t] = (uint16_t)k;
+    }
+    if ((size_t)tiles > p->tile_req_cap) {
+        if (p->d_tile_req) hipFree(p->d_tile_req);
+        p->d_tile_req = nullptr;
+        p->tile_req_cap = 0;
+        HIP_TRY(hipMalloc(&p->d_tile_req, sizeof(uint16_t) * tiles));
+        p->tile_req_cap = (size_t)tiles;
+    }
+    if (tiles > 0)
+        HIP_TRY(hipMemcpy(p->d_tile_req, tile_req.data(), sizeof(uint16_t) * tiles, hipMemcpyHostToDevice));
     HIP_TRY(hipMemcpy(p->d_reqs, p->h_reqs, sizeof(BatchReq) * nreq, hipMemcpyHostToDevice));
     HIP_TRY(hipMemcpy(p->d_segs, p->h_segs, sizeof(HistSeg) * nreq, hipMemcpyHostToDevice));
 
     BatchArgs A;
     memset(&A, 0, sizeof(A));
     A.reqs = p->d_reqs;
+    A.tile_req = p->d_tile_req;
     A.nreq = nreq;
     A.ntiles = (int32_t)tiles;
     A.tile_h = tile_h;

@@ -119,7 +119,6 @@ struct skel_plan_s {
     // plan-owned device memory (allocated on the first run)
     void* scratch[2] = {nullptr, nullptr};
     float* partials = nullptr;
-    uint32_t* ticket = nullptr;
     uint32_t* hrows = nullptr;      // image reduce: histogram rows, one per work-group
     float4* nb_acc = nullptr;
     // N-body loop graph
@@ -133,6 +132,8 @@ struct skel_plan_s {
     skel::BatchReq* h_reqs = nullptr;   // pinned host mirror of the work list
     skel::HistSeg* d_segs = nullptr;    // per-request histogram segments
     skel::HistSeg* h_segs = nullptr;
+    uint16_t* d_tile_req = nullptr;     // tile -> request table
+    size_t tile_req_cap = 0;
     uint32_t* b_rows = nullptr;         // per-tile histogram rows
     size_t b_rows_cap = 0;              // in words
     hipGraphExec_t bexec = nullptr;

@@ -110,6 +110,7 @@ struct BatchReq {
 };
 struct BatchArgs {
     const BatchReq* reqs;
+    const uint16_t* tile_req;   // request index of every tile
     int32_t nreq;
     int32_t ntiles;
     int32_t tile_h;
@@ -140,14 +141,15 @@ struct VecGroupArgs {
     int32_t in_flip, out_flip;
     int32_t ept;              // 4-float vectors per thread
     float* partials;          // per work-group partial sums (reduce) or null
-    uint32_t* ticket;         // completion counter for the final reduction
-    float* sum_out;           // final sum or null
+    float* sum_out;           // final sum (with partials)
     int32_t write_out;
     int32_t pad;
     const float* side[kMaxVecOps];
     float a[kMaxVecOps];
     uint8_t flip[kMaxVecOps];
 };
+// Launches the chain kernel and, when a.partials is set, the kernel that adds
+// the work-group partials into a.sum_out.
 hipError_t launch_vec_group(const VecGroupArgs& a, int grid, int wg, hipStream_t s, const char** kname);
 
 // -------------------------------------------------------------------- N-body

@@ -308,13 +308,15 @@ static __device__ __forceinline__ void band_tile(const ImgView& V, const OpList&
                         v.x = fin[0]; v.y = fin[1]; v.z = fin[2]; v.w = fin[3];
                     }
                     st128(v, rout, rowoff + out_vec);
-                } else if (pair) {
+                } else if (I) {
+                    // In an interior band every lane is full except the two
+                    // halo lanes of a stencil band, which store a pair.
                     const uint32_t a = pair0 ? fin[2] : fin[0];
                     const uint32_t b = pair0 ? fin[3] : fin[1];
                     u32x2 v;
                     v.x = V.out_flip ? b : a;
                     v.y = V.out_flip ? a : b;
-                    st64(v, rout, rowoff + pair_off);
+                    if (pair) st64(v, rout, rowoff + pair_off);
                 } else {
 #pragma unroll
                     for (int i = 0; i < 4; ++i)
@@ -491,9 +493,9 @@ __global__ void __launch_bounds__(256) img_band_kernel(const ImgGroupArgs A) {
 }
 
 // Persistent batched kernel: every wavefront takes tiles from a global ticket
-// counter until the work list is exhausted, finds the owning request by binary
-// search over the requests' first tile indices, runs the fused chain on the
-// tile and stores its own LDS histogram as the tile's histogram row.
+// counter until the work list is exhausted, looks up the owning request in the
+// tile -> request table, runs the fused chain on the tile and stores its own
+// LDS histogram as the tile's histogram row.
 template <int PRE, int POST, bool BLUR, bool HIST, int FL>
 __global__ void __launch_bounds__(256) img_batch_kernel(const BatchArgs A) {
     __shared__ uint32_t lh_all[HIST ? 4 * 4 * kHistWaveChan : 1];
@@ -505,12 +507,7 @@ __global__ void __launch_bounds__(256) img_batch_kernel(const BatchArgs A) {
         if (lane == 0) t = atomicAdd(A.counter, 1u);
         t = (uint32_t)wave_uniform((int)t);
         if (t >= (uint32_t)A.ntiles) break;
-        int lo = 0, hi = A.nreq - 1;
-        while (lo < hi) {   // last request with tile_begin <= t
-            const int mid = (lo + hi + 1) >> 1;
-            if (A.reqs[mid].tile_begin <= (int)t) lo = mid; else hi = mid - 1;
-        }
-        const BatchReq R = A.reqs[lo];
+        const BatchReq R = A.reqs[A.tile_req[t]];
         const int lt = (int)t - R.tile_begin;
         const int band = lt % R.nbands;
         const int chunk = lt / R.nbands;
@@ -581,10 +578,11 @@ static __device__ __forceinline__ u32x4 sum_rows(const uint32_t* base, int nrows
 }
 
 // Merge (one launch after the kernels that wrote the rows): work-group k sums
-// the rows of chunk k and adds the non-zero counts, and the channel sums they
-// imply, to its segment's outputs with device-scope atomics.  The outputs
-// were cleared before the rows were written (by hist_zero_kernel or by the
-// image kernel itself), so about (bins + 4) atomics per chunk remain.
+// the rows of chunk k.  A segment of one chunk gets its outputs written with
+// plain stores; the chunks of a longer segment add their non-zero counts, and
+// the channel sums they imply, to its outputs with device-scope atomics, the
+// outputs having been cleared before the rows were written (by
+// hist_zero_kernel or by work-group 0 of the image kernel).
 __global__ void __launch_bounds__(kFinThreads) hist_merge_kernel(const HistFinArgs F) {
     __shared__ u32x4 red[kFinThreads];
     __shared__ unsigned long long csum[4];
@@ -593,6 +591,7 @@ __global__ void __launch_bounds__(kFinThreads) hist_merge_kernel(const HistFinAr
     const int words = 4 * F.bins;
     const int r0 = S.row_begin + (k - S.chunk_begin) * S.crows;
     const int r1 = min(r0 + S.crows, S.row_begin + S.nrows);
+    const bool direct = S.nrows <= S.crows;
     if (threadIdx.x < 4) csum[threadIdx.x] = 0;
     const u32x4 n = sum_rows(F.part + (size_t)r0 * words, max(r1 - r0, 0), words, red);
     if ((int)threadIdx.x < (words >> 2)) {
@@ -600,18 +599,32 @@ __global__ void __launch_bounds__(kFinThreads) hist_merge_kernel(const HistFinAr
         const int c = b >> __builtin_ctz((unsigned)F.bins), v = b & (F.bins - 1);
         if (S.hist) {
             uint32_t* h = S.hist + c * 256 + v;
-            if (n.x) atomicAdd(h, n.x);
-            if (n.y) atomicAdd(h + 1, n.y);
-            if (n.z) atomicAdd(h + 2, n.z);
-            if (n.w) atomicAdd(h + 3, n.w);
+            if (direct) {
+                *reinterpret_cast<u32x4*>(h) = n;
+            } else {
+                if (n.x) atomicAdd(h, n.x);
+                if (n.y) atomicAdd(h + 1, n.y);
+                if (n.z) atomicAdd(h + 2, n.z);
+                if (n.w) atomicAdd(h + 3, n.w);
+            }
         }
         const unsigned long long t = (unsigned long long)v * n.x + (unsigned long long)(v + 1) * n.y +
                                      (unsigned long long)(v + 2) * n.z + (unsigned long long)(v + 3) * n.w;
         if (t) atomicAdd(&csum[c], t);
     }
+    const int per = 256 - F.bins;
+    if (direct && S.hist && (int)threadIdx.x < per) {   // bins above `bins`: 4 x per zero words
+        const int b = 4 * threadIdx.x;
+        const int c = b / per, v = F.bins + b % per;
+        *reinterpret_cast<u32x4*>(S.hist + c * 256 + v) = u32x4{0, 0, 0, 0};
+    }
     __syncthreads();
-    if (threadIdx.x < 4 && S.sum && csum[threadIdx.x])
-        atomicAdd((unsigned long long*)&S.sum[threadIdx.x], csum[threadIdx.x]);
+    if (threadIdx.x < 4 && S.sum) {
+        if (direct)
+            S.sum[threadIdx.x] = csum[threadIdx.x];
+        else if (csum[threadIdx.x])
+            atomicAdd((unsigned long long*)&S.sum[threadIdx.x], csum[threadIdx.x]);
+    }
 }
 
 // Clears the histogram and sums of every segment (one work-group each).

@@ -6,8 +6,8 @@
 // and k side vectors once and writes the output once.  A reversal is an
 // address remap: stage inputs are read at u or n-1-u of the kernel's
 // iteration coordinate u.  The sum is formed per thread, per wavefront
-// (cross-lane adds), per work-group (LDS), and the last work-group to finish
-// adds the work-group partials in a fixed order in fp64.
+// (cross-lane adds) and per work-group (LDS); a second kernel adds the
+// work-group partials in a fixed order in fp64.
 #include "kern_common.h"
 #include "kern.h"
 
@@ -21,7 +21,6 @@ static __device__ __forceinline__ float wave_sum_f32(float v) {
 
 __global__ void __launch_bounds__(1024) vec_chain_kernel(const VecGroupArgs A) {
     __shared__ float wsum[16];
-    __shared__ uint32_t last;
     const int64_t n = A.n;
     const uint32_t nbytes = (uint32_t)(n * 4);
     const __amdgpu_buffer_rsrc_t rin = mk_rsrc(A.in, nbytes);
@@ -99,8 +98,9 @@ __global__ void __launch_bounds__(1024) vec_chain_kernel(const VecGroupArgs A) {
             }
         }
     }
-    if (A.sum_out == nullptr) return;
-    // Reduce: wavefront, then work-group, then the last work-group merges.
+    if (A.partials == nullptr) return;
+    // Reduce: wavefront, then work-group (fixed order); the work-group's
+    // partial is stored, and vec_sum_merge_kernel adds the partials.
     acc = wave_sum_f32(acc);
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     if (lane == 0) wsum[wave] = acc;
@@ -109,27 +109,35 @@ __global__ void __launch_bounds__(1024) vec_chain_kernel(const VecGroupArgs A) {
         float s = 0.0f;
         for (int w = 0; w < (int)(blockDim.x >> 6); ++w) s += wsum[w];
         A.partials[blockIdx.x] = s;
-        __threadfence();
-        const uint32_t t = atomicAdd(A.ticket, 1u);
-        last = (t == gridDim.x - 1) ? 1u : 0u;
     }
+}
+
+// One 1024-thread work-group adds the n work-group partials in fp64 in a fixed
+// order (thread t: partials t, t + 1024, ...; then a tree over the threads)
+// and stores the rounded sum.  Launched after vec_chain_kernel on the same
+// stream, so no inter-work-group synchronisation is needed.
+constexpr int kMergeThreads = 1024;
+__global__ void __launch_bounds__(kMergeThreads) vec_sum_merge_kernel(const float* partials, int n, float* out) {
+    __shared__ double red[kMergeThreads];
+    double s = 0.0;
+    for (int i = threadIdx.x; i < n; i += kMergeThreads) s += (double)partials[i];
+    red[threadIdx.x] = s;
     __syncthreads();
-    if (last) {
-        __threadfence();
-        if (threadIdx.x == 0) {
-            double s = 0.0;
-            const volatile float* P = A.partials;
-            for (unsigned b = 0; b < gridDim.x; ++b) s += (double)P[b];
-            *A.sum_out = (float)s;
-            *A.ticket = 0u;   // ready for the next run
-        }
+    for (int w = kMergeThreads / 2; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
     }
+    if (threadIdx.x == 0) *out = (float)red[0];
 }
 
 hipError_t launch_vec_group(const VecGroupArgs& a, int grid, int wg, hipStream_t s, const char** kname) {
     if (kname) *kname = "vec_chain";
     if (grid <= 0) return hipSuccess;
     hipLaunchKernelGGL(vec_chain_kernel, dim3(grid), dim3(wg), 0, s, a);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess || !a.partials) return e;
+    hipLaunchKernelGGL(vec_sum_merge_kernel, dim3(1), dim3(kMergeThreads), 0, s, (const float*)a.partials, grid,
+                       a.sum_out);
     return hipGetLastError();
 }
 

@@ -199,6 +199,64 @@ extern "C" skel_status skel_config_count(skel_node root, const skel_buffer* prot
     return SKEL_OK;
 }
 
+namespace {
+
+// Times one configuration: compile, 3 warm-up runs, `reps` runs timed with
+// HIP events on a private stream; median and minimum in microseconds.
+struct Timer {
+    hipStream_t s = nullptr;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    std::vector<float> times;
+    skel_status init() {
+        HIP_TRY(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
+        HIP_TRY(hipEventCreate(&e0));
+        HIP_TRY(hipEventCreate(&e1));
+        return SKEL_OK;
+    }
+    ~Timer() {
+        if (e0) hipEventDestroy(e0);
+        if (e1) hipEventDestroy(e1);
+        if (s) hipStreamDestroy(s);
+    }
+    skel_status time(skel_node root, const skel_buffer* args, int32_t nargs, const Config& c, int reps,
+                     double* med, double* mn) {
+        skel_plan_opts o;
+        config_to_opts(c, &o);
+        skel_plan p = nullptr;
+        skel_status st = skel_plan_compile(root, args, nargs, &o, &p);
+        if (st) return SKEL_EINVAL;
+        for (int w = 0; w < 3 && !st; ++w) st = skel_plan_run(p, args, nargs, s);
+        times.clear();
+        for (int r = 0; r < reps && !st; ++r) {
+            hipEventRecord(e0, s);
+            st = skel_plan_run(p, args, nargs, s);
+            hipEventRecord(e1, s);
+            hipEventSynchronize(e1);
+            float ms = 0;
+            hipEventElapsedTime(&ms, e0, e1);
+            times.push_back(ms * 1000.0f);
+        }
+        hipStreamSynchronize(s);
+        skel_plan_destroy(p);
+        if (st) return st == SKEL_EINVAL ? SKEL_EDEVICE : st;
+        std::sort(times.begin(), times.end());
+        *med = times[times.size() / 2];
+        *mn = times.front();
+        return SKEL_OK;
+    }
+};
+
+void db_row(FILE* db, const std::string& key, const Linear& L, const Shape& sh, const Config& c, double med,
+            double mn) {
+    float f[kNumFeatures];
+    features(L, sh, c, f);
+    fprintf(db, "%s,%d,%u,%d,%d,%d,%d", key.c_str(), c.fusion, c.split_mask, c.tile_h, c.wg, c.ept, c.variant);
+    for (int i = 0; i < kNumFeatures; ++i) fprintf(db, ",%.6g", (double)f[i]);
+    fprintf(db, ",%.4f,%.4f\n", med, mn);
+}
+
+}  // namespace
+
 extern "C" skel_status skel_tune(skel_node root, const skel_buffer* args, int32_t nargs, const char* db_path,
                                  int32_t reps, int32_t max_configs, uint64_t sample_seed, skel_plan_opts* best,
                                  double* best_us) {
@@ -230,59 +288,181 @@ extern "C" skel_status skel_tune(skel_node root, const skel_buffer* args, int32_
         if (!db) return set_error(SKEL_EINVAL, "cannot open %s", db_path);
     }
     const std::string key = composition_key(L, sh);
-    hipStream_t s;
-    HIP_TRY(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
-    hipEvent_t e0, e1;
-    hipEventCreate(&e0);
-    hipEventCreate(&e1);
+    Timer T;
+    if ((st = T.init())) {
+        if (db) fclose(db);
+        return st;
+    }
     double best_t = 1e300;
     Config best_c = cands[0];
-    std::vector<float> times;
     skel_status result = SKEL_OK;
     for (const Config& c : cands) {
-        skel_plan_opts o;
-        config_to_opts(c, &o);
-        skel_plan p = nullptr;
-        st = skel_plan_compile(root, args, nargs, &o, &p);
-        if (st) continue;
-        for (int w = 0; w < 3 && !st; ++w) st = skel_plan_run(p, args, nargs, s);
-        times.clear();
-        for (int r = 0; r < reps && !st; ++r) {
-            hipEventRecord(e0, s);
-            st = skel_plan_run(p, args, nargs, s);
-            hipEventRecord(e1, s);
-            hipEventSynchronize(e1);
-            float ms = 0;
-            hipEventElapsedTime(&ms, e0, e1);
-            times.push_back(ms * 1000.0f);
-        }
-        hipStreamSynchronize(s);
-        skel_plan_destroy(p);
+        double med = 0, mn = 0;
+        st = T.time(root, args, nargs, c, reps, &med, &mn);
+        if (st == SKEL_EINVAL) continue;   // configuration rejected by the plan compiler
         if (st) {
             result = st;
             break;
         }
-        std::sort(times.begin(), times.end());
-        const double med = times[times.size() / 2];
         if (med < best_t) {
             best_t = med;
             best_c = c;
         }
-        if (db) {
-            float f[kNumFeatures];
-            features(L, sh, c, f);
-            fprintf(db, "%s,%d,%u,%d,%d,%d,%d", key.c_str(), c.fusion, c.split_mask, c.tile_h, c.wg, c.ept,
-                    c.variant);
-            for (int i = 0; i < kNumFeatures; ++i) fprintf(db, ",%.6g", (double)f[i]);
-            fprintf(db, ",%.4f,%.4f\n", med, (double)times.front());
-        }
+        if (db) db_row(db, key, L, sh, c, med, mn);
     }
     if (db) fclose(db);
-    hipEventDestroy(e0);
-    hipEventDestroy(e1);
-    hipStreamDestroy(s);
     if (result) return result;
     config_to_opts(best_c, best);
     if (best_us) *best_us = best_t;
+    return SKEL_OK;
+}
+
+// Algorithm 1 (the profile builder), on one GPU: the dimensions of the
+// configuration space are walked in the order most likely to hold the best
+// configuration, and a dimension is abandoned as soon as a candidate fails to
+// improve on the best so far ("discard"):
+//   1. fusion partitions, fewest kernels first (the fully fused plan leads);
+//      after the first partition, a partition whose best time does not beat
+//      the best so far ends the search;
+//   2. per partition, work-group sizes in non-increasing order of occupancy
+//      (resident wavefronts per CU), those below occ_threshold of the best
+//      occupancy filtered out; a size that does not improve ends the loop;
+//   3. per size, the inner parameter (tile height of images, vectors per
+//      thread of fp32 chains, j-slices of N-body) in increasing order while
+//      each step improves by at least `precision_us`.
+// CPU fission, overlap and the CPU/GPU load distribution of the paper's
+// algorithm have no counterpart on one GPU.
+namespace {
+
+struct Group {
+    int wg;
+    std::vector<Config> inner;   // increasing inner parameter
+};
+
+int occupancy_of(const Linear& L, const Shape& sh, const Config& c) {
+    std::vector<Kernel> ks;
+    if (build_kernels(L, sh, c, ks) || ks.empty()) return 0;
+    if (L.dom == DOM_U8) {
+        int worst = 1 << 30;
+        for (const Kernel& K : ks)
+            worst = std::min(worst, img_waves_per_cu(K.img, K.blur, K.reduce, K.wg, c.variant));
+        return worst;
+    }
+    return 1;   // fp32 chains and N-body: no LDS, occupancy does not depend on wg here
+}
+
+int inner_value(const Linear& L, const Config& c) { return L.dom == DOM_F32 ? c.ept : c.tile_h; }
+
+}  // namespace
+
+extern "C" skel_status skel_tune_pruned(skel_node root, const skel_buffer* args, int32_t nargs, const char* db_path,
+                                        int32_t reps, double precision_us, double occ_threshold,
+                                        skel_plan_opts* best, double* best_us, int32_t* timed) {
+    clear_error();
+    if (!root || !best) return set_error(SKEL_EINVAL, "null root or result");
+    Linear L;
+    Shape sh;
+    skel_status st = linearize(root, L);
+    if (!st && L.dom == DOM_NONE) L.dom = (nargs > 0 && args[0].dtype == SKEL_U8) ? DOM_U8 : DOM_F32;
+    if (!st) st = derive_shape(L, args, nargs, sh);
+    if (st) return st;
+    if (reps <= 0) reps = 10;
+    if (precision_us < 0) precision_us = 0;
+    const std::vector<Config> all = enumerate_configs(L, sh);
+    if (all.empty()) return set_error(SKEL_EUNSUPPORTED, "no valid configuration");
+
+    // Group the candidate set by partition, then by work-group size.
+    struct Part {
+        int kernels;
+        int fusion;
+        uint32_t mask;
+        std::vector<Group> groups;
+    };
+    std::vector<Part> parts;
+    for (const Config& c : all) {
+        Part* P = nullptr;
+        for (Part& q : parts)
+            if (q.fusion == c.fusion && q.mask == c.split_mask) P = &q;
+        if (!P) {
+            std::vector<Kernel> ks;
+            build_kernels(L, sh, c, ks);
+            parts.push_back(Part{(int)ks.size(), c.fusion, c.split_mask, {}});
+            P = &parts.back();
+        }
+        Group* G = nullptr;
+        for (Group& g : P->groups)
+            if (g.wg == c.wg) G = &g;
+        if (!G) {
+            P->groups.push_back(Group{c.wg, {}});
+            G = &P->groups.back();
+        }
+        G->inner.push_back(c);
+    }
+    std::stable_sort(parts.begin(), parts.end(), [](const Part& a, const Part& b) {
+        if (a.kernels != b.kernels) return a.kernels < b.kernels;
+        return a.mask < b.mask;
+    });
+    for (Part& P : parts) {
+        std::vector<std::pair<int, int>> occ;   // (occupancy, index)
+        for (size_t i = 0; i < P.groups.size(); ++i) {
+            std::sort(P.groups[i].inner.begin(), P.groups[i].inner.end(),
+                      [&](const Config& a, const Config& b) { return inner_value(L, a) < inner_value(L, b); });
+            occ.push_back({occupancy_of(L, sh, P.groups[i].inner[0]), (int)i});
+        }
+        std::stable_sort(occ.begin(), occ.end(),
+                         [](const std::pair<int, int>& a, const std::pair<int, int>& b) { return a.first > b.first; });
+        std::vector<Group> ordered;
+        for (const auto& o : occ)
+            if (o.first >= occ_threshold * occ.front().first) ordered.push_back(P.groups[o.second]);
+        P.groups.swap(ordered);
+    }
+
+    FILE* db = nullptr;
+    if (db_path && *db_path) {
+        db = fopen(db_path, "a");
+        if (!db) return set_error(SKEL_EINVAL, "cannot open %s", db_path);
+    }
+    const std::string key = composition_key(L, sh);
+    Timer T;
+    if ((st = T.init())) {
+        if (db) fclose(db);
+        return st;
+    }
+    double best_t = 1e300;
+    Config best_c = parts.front().groups.front().inner.front();
+    int ntimed = 0;
+    skel_status result = SKEL_OK;
+    for (size_t pi = 0; pi < parts.size() && !result; ++pi) {
+        const double before_part = best_t;
+        for (const Group& G : parts[pi].groups) {
+            const double before_group = best_t;
+            for (const Config& c : G.inner) {
+                double med = 0, mn = 0;
+                st = T.time(root, args, nargs, c, reps, &med, &mn);
+                if (st == SKEL_EINVAL) continue;
+                if (st) {
+                    result = st;
+                    break;
+                }
+                ++ntimed;
+                if (db) db_row(db, key, L, sh, c, med, mn);
+                if (med < best_t) {
+                    const double gain = best_t - med;
+                    best_t = med;
+                    best_c = c;
+                    if (gain < precision_us) break;   // converged along this direction
+                } else {
+                    break;                            // no improvement: discard larger values
+                }
+            }
+            if (result || !(best_t < before_group)) break;   // this size did not improve: discard the rest
+        }
+        if (pi > 0 && !(best_t < before_part)) break;        // this partition did not improve: stop
+    }
+    if (db) fclose(db);
+    if (result) return result;
+    config_to_opts(best_c, best);
+    if (best_us) *best_us = best_t;
+    if (timed) *timed = ntimed;
     return SKEL_OK;
 }

@@ -2,10 +2,9 @@
 into the short text summaries kept under ``profiles/``.
 
 The counter passes are taken one counter group per run (rocprofv3 does not
-split counters over passes):
+split counters over passes), from the repository root with TMPDIR=/tmp:
 
-  rocprofv3 --kernel-trace --stats -d DIR -o cfg2 --output-format csv -- python3 bench.py \
-      --steps 20 --warmup 5 --no-extras --no-cpu-baseline
+  rocprofv3 --kernel-trace --stats -d DIR -o all --output-format csv -- python3 bench.py --no-cpu-baseline
   rocprofv3 --pmc FETCH_SIZE -d DIR -o fetch --output-format csv -- python3 bench.py --profile-run --steps 5
   rocprofv3 --pmc WRITE_SIZE -d DIR -o write --output-format csv -- python3 bench.py --profile-run --steps 5
   rocprofv3 --pmc SQ_WAVES SQ_INSTS_VALU SQ_INSTS_LDS SQ_LDS_BANK_CONFLICT SQ_ACTIVE_INST_VALU \
@@ -17,7 +16,7 @@ the same image; FETCH_SIZE / WRITE_SIZE (KiB per dispatch) of the fused kernel
 are scaled by (known bytes / counter reading) of the copy kernel, which
 corrects for the share of the memory channels the counters observe.
 
-  python -m paper_1510_06585_amd.rocprof_harness --trace DIR/cfg2_kernel_stats.csv \
+  python -m paper_1510_06585_amd.rocprof_harness --trace DIR/all_kernel_stats.csv \
       --fetch DIR/fetch_counter_collection.csv --write DIR/write_counter_collection.csv \
       --sq DIR/sq_counter_collection.csv --out profiles/
 """
@@ -36,14 +35,13 @@ FUSED_NAME = "img_noise_sol_blur_reduce"
 COPY = "img_band_kernel<0, 0, false, false, 0>"
 COPY_BYTES = 2 * 8192 * 8192 * 4
 COMMANDS = (
-    "rocprofv3 --kernel-trace --stats -d DIR -o cfg2 --output-format csv -- python3 bench.py "
-    "--steps 20 --warmup 5 --no-extras --no-cpu-baseline",
+    "rocprofv3 --kernel-trace --stats -d DIR -o all --output-format csv -- python3 bench.py --no-cpu-baseline",
     "rocprofv3 --pmc FETCH_SIZE -d DIR -o fetch --output-format csv -- python3 bench.py --profile-run --steps 5",
     "rocprofv3 --pmc WRITE_SIZE -d DIR -o write --output-format csv -- python3 bench.py --profile-run --steps 5",
     "rocprofv3 --pmc SQ_WAVES SQ_INSTS_VALU SQ_INSTS_LDS SQ_LDS_BANK_CONFLICT SQ_ACTIVE_INST_VALU "
     "SQ_ACTIVE_INST_LDS SQ_BUSY_CYCLES SQ_WAVE_CYCLES -d DIR -o sq --output-format csv -- "
     "python3 bench.py --profile-run --steps 3",
-    "python -m paper_1510_06585_amd.rocprof_harness --trace DIR/cfg2_kernel_stats.csv "
+    "python -m paper_1510_06585_amd.rocprof_harness --trace DIR/all_kernel_stats.csv "
     "--fetch DIR/fetch_counter_collection.csv --write DIR/write_counter_collection.csv "
     "--sq DIR/sq_counter_collection.csv --out profiles/",
 )
@@ -101,7 +99,8 @@ def main():
            "bytes_per_launch": round(tr["bytes_per_launch"]),
            "algorithmic_bytes": 2 * 8192 * 8192 * 4 + 4128, **{k: round(v, 4) for k, v in tr.items()}}
     json.dump(rec, open(os.path.join(a.out, f"traffic_{FUSED_NAME}.json"), "w"), indent=1)
-    lines = ["# rocprofv3 summary: fused Pipeline+MapReduce, 8192x8192 RGBA u8 (and the plain plan's kernels)",
+    lines = ["# rocprofv3 summary: fused Pipeline+MapReduce, 8192x8192 RGBA u8 (kernel trace of the whole "
+             "bench run: every skeleton's kernels)",
              "", "Commands (repository root on the GPU box, TMPDIR=/tmp):", "", "```"] + list(COMMANDS)
     lines += ["```", "", "## Kernel trace (--kernel-trace --stats)", "",
               "| kernel | calls | avg us | min us | max us |", "|---|---|---|---|---|"]

@@ -86,6 +86,10 @@ _SIGS = {
     "skel_tune": (ctypes.c_int32, [_node_p, ctypes.POINTER(Buffer), ctypes.c_int32, ctypes.c_char_p,
                                    ctypes.c_int32, ctypes.c_int32, ctypes.c_uint64, ctypes.POINTER(PlanOpts),
                                    ctypes.POINTER(ctypes.c_double)]),
+    "skel_tune_pruned": (ctypes.c_int32, [_node_p, ctypes.POINTER(Buffer), ctypes.c_int32, ctypes.c_char_p,
+                                          ctypes.c_int32, ctypes.c_double, ctypes.c_double,
+                                          ctypes.POINTER(PlanOpts), ctypes.POINTER(ctypes.c_double),
+                                          ctypes.POINTER(ctypes.c_int32)]),
     "skel_config_count": (ctypes.c_int32, [_node_p, ctypes.POINTER(Buffer), ctypes.c_int32,
                                            ctypes.POINTER(ctypes.c_int32)]),
     "skel_feature_count": (ctypes.c_int32, []),
@@ -329,6 +333,20 @@ def tune(root: Node, args, db_path: str | None = None, reps: int = 10, max_confi
     _check(lib().skel_tune(root.handle, arr, n, db_path.encode() if db_path else None, reps, max_configs,
                            sample_seed, ctypes.byref(best), ctypes.byref(us)))
     return best.as_dict(), us.value
+
+
+def tune_pruned(root: Node, args, db_path: str | None = None, reps: int = 10, precision_us: float = 0.0,
+                occ_threshold: float = 0.0):
+    """Algorithm-1 style search (skel_tune_pruned); returns (options, median us,
+    number of configurations timed)."""
+    arr, n = _buf_array(args)
+    best = PlanOpts()
+    us = ctypes.c_double()
+    timed = ctypes.c_int32()
+    _check(lib().skel_tune_pruned(root.handle, arr, n, db_path.encode() if db_path else None, reps,
+                                  precision_us, occ_threshold, ctypes.byref(best), ctypes.byref(us),
+                                  ctypes.byref(timed)))
+    return best.as_dict(), us.value, timed.value
 
 
 def config_count(root: Node, protos) -> int:

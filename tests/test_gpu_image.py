@@ -3,6 +3,7 @@ histograms and sums, for fused, unfused and interpreted kernels, at the full
 benchmark sizes, at the paper's odd image sizes and at ragged tiny sizes."""
 import numpy as np
 import pytest
+import torch
 
 import oracle
 import paper_1510_06585_amd as sk
@@ -138,6 +139,27 @@ def test_empty_images_and_reduce_outputs_overwritten():
     out, h, s = image_results(args, "hist_sum")
     ref, rh, rs = oracle.run_image_pipeline(img, CFG2, "hist_sum")
     assert (h == rh).all() and (s == rs).all()
+
+
+@pytest.mark.parametrize("options", [{"wg": 64, "tile_h": 8}, {}, {"fusion": sk.FUSE_OFF, "tile_h": 4}],
+                         ids=["many-rows", "auto", "plain"])
+def test_reduce_rerun_overwrites_with_many_merge_chunks(options):
+    """Plans whose histogram rows need several merge chunks (device atomics into
+    outputs cleared by the image kernel) and plans with one chunk (plain
+    stores), run three times on the same output buffers with new input data."""
+    from gpu_helpers import image_args, image_results
+    H, W = 1500, 2048
+    args = image_args(synth.image(21, H, W), "hist_sum")
+    p = sk.Plan(sk.image_chain(CFG2, "hist_sum"), args, options)
+    for r in range(3):
+        img = synth.image(21 + r, H, W)
+        args[0].copy_(torch.from_numpy(img).cuda())
+        p.run(args)
+        out, h, s = image_results(args, "hist_sum")
+        ref, rh, rs = oracle.run_image_pipeline(img, CFG2, "hist_sum")
+        assert_image_equal(out, ref, f"run {r}")
+        assert (h == rh).all() and (s == rs).all(), f"run {r}"
+    p.destroy()
 
 
 def test_sum_only_reduce():
