@@ -14,9 +14,10 @@ plan and tile configuration for compositions it has never seen:
    (exhaustive: its best is the reference);
 3. train the MLP on the GPU (skel_cost_train) and let it pick a configuration
    for each held-out composition (skel_cost_select);
-4. report the regret t(chosen) / t(best) - 1 next to three baselines: the
-   default plan, nearest-neighbour derivation over the training rows, and the
-   untrained network.
+4. report the regret t(chosen) / t(best) - 1 next to the baselines: the
+   default plan, nearest-neighbour derivation over the training rows, the
+   untrained network, a random configuration, and the paper's own search
+   (Algorithm 1, skel_tune_pruned) with the number of configurations it times.
 
 Inputs are seeded random device tensors: runtimes do not depend on values.
 """
@@ -140,7 +141,7 @@ def experiment(n_train: int = 1000, n_test: int = 200, per_train: int = 20, seed
             log(f"train {i}/{len(train)} {time.time() - t0:.0f}s")
     n_labels = len(_read_rows(train_db))
     t_train_labels = time.time() - t0
-    test_rows, defaults = [], []
+    test_rows, defaults, pruned = [], [], []
     for i, c in enumerate(test):
         root = sk.image_chain(c["stages"], c["reduce"])
         args = _args_for(c, gen)
@@ -149,6 +150,8 @@ def experiment(n_train: int = 1000, n_test: int = 200, per_train: int = 20, seed
         rows = _read_rows(test_db)[before:]
         test_rows.append(rows)
         defaults.append(_time_default(root, args))
+        popts, _, ptimed = sk.tune_pruned(root, args, None, reps=10)
+        pruned.append((popts, ptimed))
         del args
         if i % 20 == 0:
             log(f"test {i}/{len(test)} {time.time() - t0:.0f}s")
@@ -167,8 +170,9 @@ def experiment(n_train: int = 1000, n_test: int = 200, per_train: int = 20, seed
     mu, sd = F.mean(0), F.std(0)
     sd[sd < 1e-6] = 1.0
     Fz = (F - mu) / sd
-    reg = {"model": [], "default": [], "nearest_neighbour": [], "untrained": [], "random": []}
-    for c, rows, tdef in zip(test, test_rows, defaults):
+    reg = {"model": [], "default": [], "nearest_neighbour": [], "untrained": [], "random": [],
+           "pruned_tuner": []}
+    for c, rows, tdef, (popts, _) in zip(test, test_rows, defaults, pruned):
         root = sk.image_chain(c["stages"], c["reduce"])
         protos = _args_for_proto(c)
         best = min(r["t"] for r in rows)
@@ -182,10 +186,13 @@ def experiment(n_train: int = 1000, n_test: int = 200, per_train: int = 20, seed
         pred = T[d2.argmin(1)]
         reg["nearest_neighbour"].append(rows[int(pred.argmin())]["t"] / best - 1.0)
         reg["random"].append(rows[int(rng.integers(0, len(rows)))]["t"] / best - 1.0)
+        t = _match(rows, popts)
+        reg["pruned_tuner"].append((t if t is not None else tdef) / best - 1.0)
     return {
         "experiment": "learned config selector",
         "train_compositions": len(train), "heldout_compositions": len(test), "labels": n_labels,
         "heldout_configs_timed": int(sum(len(r) for r in test_rows)),
+        "pruned_tuner_configs_timed": int(sum(t for _, t in pruned)),
         "final_train_loss_log_us2": round(float(loss), 5), "untrained_loss": round(float(loss0), 5),
         "train_seconds_gpu": round(t_train, 2), "label_seconds": round(t_labels, 1),
         "train_label_seconds": round(t_train_labels, 1),
