@@ -4,6 +4,7 @@ into the short text summaries kept under ``profiles/``.
 The counter passes are taken one counter group per run (rocprofv3 does not
 split counters over passes), from the repository root with TMPDIR=/tmp:
 
+  rocprofv3 --kernel-trace --stats -d DIR -o cfg2 --output-format csv -- python3 bench.py --no-extras --no-cpu-baseline
   rocprofv3 --kernel-trace --stats -d DIR -o all --output-format csv -- python3 bench.py --no-cpu-baseline
   rocprofv3 --pmc FETCH_SIZE -d DIR -o fetch --output-format csv -- python3 bench.py --profile-run --steps 5
   rocprofv3 --pmc WRITE_SIZE -d DIR -o write --output-format csv -- python3 bench.py --profile-run --steps 5
@@ -16,9 +17,9 @@ the same image; FETCH_SIZE / WRITE_SIZE (KiB per dispatch) of the fused kernel
 are scaled by (known bytes / counter reading) of the copy kernel, which
 corrects for the share of the memory channels the counters observe.
 
-  python -m paper_1510_06585_amd.rocprof_harness --trace DIR/all_kernel_stats.csv \
-      --fetch DIR/fetch_counter_collection.csv --write DIR/write_counter_collection.csv \
-      --sq DIR/sq_counter_collection.csv --out profiles/
+  python -m paper_1510_06585_amd.rocprof_harness --trace DIR/cfg2_kernel_stats.csv \
+      --trace-all DIR/all_kernel_stats.csv --fetch DIR/fetch_counter_collection.csv \
+      --write DIR/write_counter_collection.csv --sq DIR/sq_counter_collection.csv --out profiles/
 """
 from __future__ import annotations
 
@@ -35,15 +36,17 @@ FUSED_NAME = "img_noise_sol_blur_reduce"
 COPY = "img_band_kernel<0, 0, false, false, 0>"
 COPY_BYTES = 2 * 8192 * 8192 * 4
 COMMANDS = (
+    "rocprofv3 --kernel-trace --stats -d DIR -o cfg2 --output-format csv -- python3 bench.py --no-extras "
+    "--no-cpu-baseline",
     "rocprofv3 --kernel-trace --stats -d DIR -o all --output-format csv -- python3 bench.py --no-cpu-baseline",
     "rocprofv3 --pmc FETCH_SIZE -d DIR -o fetch --output-format csv -- python3 bench.py --profile-run --steps 5",
     "rocprofv3 --pmc WRITE_SIZE -d DIR -o write --output-format csv -- python3 bench.py --profile-run --steps 5",
     "rocprofv3 --pmc SQ_WAVES SQ_INSTS_VALU SQ_INSTS_LDS SQ_LDS_BANK_CONFLICT SQ_ACTIVE_INST_VALU "
     "SQ_ACTIVE_INST_LDS SQ_BUSY_CYCLES SQ_WAVE_CYCLES -d DIR -o sq --output-format csv -- "
     "python3 bench.py --profile-run --steps 3",
-    "python -m paper_1510_06585_amd.rocprof_harness --trace DIR/all_kernel_stats.csv "
-    "--fetch DIR/fetch_counter_collection.csv --write DIR/write_counter_collection.csv "
-    "--sq DIR/sq_counter_collection.csv --out profiles/",
+    "python -m paper_1510_06585_amd.rocprof_harness --trace DIR/cfg2_kernel_stats.csv "
+    "--trace-all DIR/all_kernel_stats.csv --fetch DIR/fetch_counter_collection.csv "
+    "--write DIR/write_counter_collection.csv --sq DIR/sq_counter_collection.csv --out profiles/",
 )
 
 
@@ -88,6 +91,7 @@ def main():
     ap.add_argument("--fetch", required=True)
     ap.add_argument("--write", required=True)
     ap.add_argument("--sq")
+    ap.add_argument("--trace-all", help="kernel stats of the whole bench run (every skeleton)")
     ap.add_argument("--out", required=True)
     a = ap.parse_args()
     os.makedirs(a.out, exist_ok=True)
@@ -99,8 +103,8 @@ def main():
            "bytes_per_launch": round(tr["bytes_per_launch"]),
            "algorithmic_bytes": 2 * 8192 * 8192 * 4 + 4128, **{k: round(v, 4) for k, v in tr.items()}}
     json.dump(rec, open(os.path.join(a.out, f"traffic_{FUSED_NAME}.json"), "w"), indent=1)
-    lines = ["# rocprofv3 summary: fused Pipeline+MapReduce, 8192x8192 RGBA u8 (kernel trace of the whole "
-             "bench run: every skeleton's kernels)",
+    lines = ["# rocprofv3 summary: fused Pipeline+MapReduce, 8192x8192 RGBA u8 (config-2 bench run: fused "
+             "plan, plain plan, copy reference)",
              "", "Commands (repository root on the GPU box, TMPDIR=/tmp):", "", "```"] + list(COMMANDS)
     lines += ["```", "", "## Kernel trace (--kernel-trace --stats)", "",
               "| kernel | calls | avg us | min us | max us |", "|---|---|---|---|---|"]
@@ -117,6 +121,16 @@ def main():
             for c, v in sorted(_find(sq, kern).items()):
                 lines.append(f"| `{kern}` | {c} | {v:.0f} |")
     open(os.path.join(a.out, f"{FUSED_NAME}_8192.md"), "w").write("\n".join(lines) + "\n")
+    if a.trace_all:
+        al = ["# rocprofv3 kernel trace of the whole bench run (every skeleton's kernels)", "",
+              "Command (repository root on the GPU box, TMPDIR=/tmp):", "", "```", COMMANDS[1], "```", "",
+              "Averages mix workloads where one kernel serves several (e.g. the fused image kernel runs the "
+              "8192^2 image and, in the sequential baseline of the batch, 256 smaller ones).", "",
+              "| kernel | calls | avg us | min us | max us |", "|---|---|---|---|---|"]
+        for r in kernel_stats(a.trace_all):
+            al.append(f"| `{r['name'][:90]}` | {r['calls']} | {r['avg_ns']/1e3:.2f} | {r['min_ns']/1e3:.2f} | "
+                      f"{r['max_ns']/1e3:.2f} |")
+        open(os.path.join(a.out, "bench_all_kernels.md"), "w").write("\n".join(al) + "\n")
     print(json.dumps(rec))
 
 
