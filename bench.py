@@ -287,6 +287,51 @@ def bench_batch():
     return res
 
 
+def bench_while():
+    """While Loop with the device-evaluated condition vs the paper's host-side
+    evaluation (run the body, read its sums back, test on the host) on the
+    config-2 body over 8192^2, 10 iterations."""
+    import numpy as np
+    import torch
+    import paper_1510_06585_amd as sk
+    import synth
+    H = W = 8192
+    iters = 10
+    img = synth.image(synth.SEED_PIPE_FUSED, H, W)
+    x = torch.from_numpy(img).cuda()
+    y = torch.empty_like(x)
+    hist = torch.zeros(4, 256, dtype=torch.int32, device="cuda")
+    sums = torch.zeros(4, dtype=torch.int64, device="cuda")
+    count = torch.zeros(1, dtype=torch.int32, device="cuda")
+    body = sk.image_chain(CFG2, "hist_sum")
+    res = {"iterations": iters}
+    wplan = sk.Plan(sk.LoopWhile(body, iters, 0, ">=", 0), [x, y, hist, sums, count])
+    wb = sk.bind([x, y, hist, sums, count])
+    _, ms = timed_runs(lambda: wplan.run(wb), 10, 3)
+    res["device_condition_ms_per_iteration"] = round(ms / 10 / iters, 5)
+    assert int(count.cpu().numpy().view(np.uint32)[0]) == iters
+    wplan.destroy()
+    bplan = sk.Plan(body, [x, y, hist, sums])
+    a, b2 = sk.bind([x, y, hist, sums]), sk.bind([y, x, hist, sums])
+
+    def host_loop():
+        for i in range(iters):
+            bplan.run(a if i % 2 == 0 else b2)
+            s = sums.cpu().numpy().view(np.uint64)       # the host reads the state and tests it
+            if not int(s[0]) >= 0:
+                break
+    _, ms = timed_runs(host_loop, 5, 1)
+    res["host_condition_ms_per_iteration"] = round(ms / 5 / iters, 5)
+
+    def counted():
+        for i in range(iters):
+            bplan.run(a if i % 2 == 0 else b2)
+    _, ms = timed_runs(counted, 5, 1)
+    res["no_condition_ms_per_iteration"] = round(ms / 5 / iters, 5)
+    bplan.destroy()
+    return res
+
+
 def profile_run(steps):
     """Short run for hardware-counter passes: the fused config-2 kernel and a
     plain copy of the same image (the byte-count reference), `steps` each."""
@@ -349,6 +394,8 @@ def main():
         extras["nbody_65536_x20"] = bench_nbody()
         log("config 4: 256 batched uneven requests")
         extras["batched_256"] = bench_batch()
+        log("while Loop: device-evaluated condition, 8192x8192 x 10")
+        extras["while_loop_8192x10"] = bench_while()
         out["extras"] = extras
     if not a.no_cpu_baseline:
         log("cpu baseline: oracle on the host")

@@ -128,6 +128,22 @@ typedef struct skel_loop_state {
     int32_t global_sync;
 } skel_loop_state;
 
+/* Stop condition of a while Loop (Sec. 2.1: Loop covers while loops; the
+ * state holds the stoppage condition).  After every iteration the loop
+ * continues while  sum[channel] <cmp> threshold  holds for the uint64
+ * channel sums of the body's reduce output, and fewer than the state's
+ * `iterations` iterations have run.  The condition is evaluated on the device;
+ * the host reads a one-word flag every check_every iterations (0 = 8) to
+ * decide whether to enqueue more. */
+enum { SKEL_CMP_GT = 0, SKEL_CMP_GE = 1, SKEL_CMP_LT = 2, SKEL_CMP_LE = 3 };
+typedef struct skel_loop_cond {
+    int32_t channel;      /* 0..3 */
+    int32_t cmp;          /* SKEL_CMP_* */
+    uint64_t threshold;
+    int32_t check_every;  /* iterations between host checks of the device flag; 0 = 8 */
+    int32_t reserved;
+} skel_loop_cond;
+
 /* -------------------------------------------------------- plan options */
 enum { SKEL_FUSE_AUTO = -1, SKEL_FUSE_OFF = 0, SKEL_FUSE_ON = 1, SKEL_FUSE_MASK = 2 };
 enum { SKEL_SELECT_DEFAULT = 0, SKEL_SELECT_DB = 1, SKEL_SELECT_MODEL = 2, SKEL_SELECT_EXHAUSTIVE = 3 };
@@ -192,6 +208,22 @@ skel_status skel_mapreduce(skel_node map, int32_t red, skel_node* out);
  * Pipeline(NBODY_FORCE, LEAPFROG) keeps its state on the device and is
  * captured into one HIP graph. */
 skel_status skel_loop(skel_node body, const skel_loop_state* st, skel_node* out);
+
+/* While Loop(body, state, cond) with a device-evaluated stop condition (the
+ * paper evaluates a Loop's condition and updates its state on the host,
+ * Sec. 3.1; here both stay on the device).  body must be a MapReduce over an
+ * image chain (SKEL_RED_HIST256_SUM or SKEL_RED_SUM); st->iterations >= 1 is
+ * the iteration limit; carried_mask and global_sync are recorded.  Valid only
+ * at the root of a plan.  A run computes
+ *     x = in; count = 0;
+ *     do { (x, hist, sum) = body(x); ++count; }
+ *     while (count < st->iterations && sum[cond->channel] <cmp> threshold);
+ * and writes out = x, hist/sum of the last iteration and count.  Plan
+ * arguments: in u8 [H,W,4], out u8 [H,W,4], [hist u32 [4,256],] sum u64 [4],
+ * count u32 [1]; in and out must not overlap.  Unlike other runs, a run of a
+ * while plan synchronises `stream` every cond->check_every iterations. */
+skel_status skel_loop_while(skel_node body, const skel_loop_state* st, const skel_loop_cond* cond,
+                            skel_node* out);
 
 /* Drops one reference; frees the node when none remain. NULL is a no-op. */
 skel_status skel_node_release(skel_node node);

@@ -163,6 +163,25 @@ def run_image_pipeline(img: np.ndarray, stages, reduce: str | None = None):
     raise ValueError(reduce)
 
 
+_CMP = {">": lambda v, t: v > t, ">=": lambda v, t: v >= t, "<": lambda v, t: v < t, "<=": lambda v, t: v <= t}
+
+
+def run_image_while(img: np.ndarray, stages, reduce: str, channel: int, cmp: str, threshold: int,
+                    max_iterations: int):
+    """While Loop over a MapReduce body (Sec. 2.1, Loop: while loops; its state holds
+    the stop condition): run the body (``stages`` then ``reduce``) on the current
+    image, count the iteration, and repeat while ``sum[channel] cmp threshold``
+    holds and fewer than ``max_iterations`` iterations have run (the body runs at
+    least once).  Returns ``(out, hist, sum, count)``."""
+    cur = _img(img)
+    count = 0
+    while True:
+        cur, hist, s = run_image_pipeline(cur, stages, reduce)
+        count += 1
+        if count >= max_iterations or not _CMP[cmp](int(s[channel]), int(threshold)):
+            return cur, hist, s, count
+
+
 # ------------------------------------------------------------------ fp32 stages
 def _f32(a: np.ndarray) -> np.ndarray:
     a = np.ascontiguousarray(a)

@@ -85,6 +85,13 @@ skel_status check_args(skel_plan p, const skel_buffer* args, int32_t nargs) {
 
 skel_status check_aliasing(skel_plan p, const skel_buffer* args) {
     const Linear& L = p->lin;
+    if (L.dom == DOM_U8 && L.is_while) {
+        const int n = (int)p->proto.size();
+        for (int a = 0; a < n; ++a)
+            for (int b = a + 1; b < n; ++b)
+                if (overlap(args[a], args[b])) return set_error(SKEL_EINVAL, "while Loop arguments must not overlap");
+        return SKEL_OK;
+    }
     if (L.dom == DOM_U8) {
         const bool same = args[0].data == args[1].data && range_of(args[0]).hi > range_of(args[0]).lo;
         if (overlap(args[0], args[1]) && !same) return set_error(SKEL_EINVAL, "input and output overlap partially");
@@ -157,6 +164,71 @@ skel_status run_image(skel_plan p, const skel_buffer* args, hipStream_t s) {
             HIP_TRY(A.ntiles > 0 ? launch_hist_merge(F, s) : launch_hist_zero(F, s));
         }
     }
+    return SKEL_OK;
+}
+
+// While Loop (skel_loop_while): iteration i (from 0) reads the previous
+// iteration's image (the input for i = 0) and writes out when i is even, the
+// plan's second image otherwise; every kernel of an iteration is guarded by
+// the device flag, which the step kernel clears when the condition fails or
+// the limit is reached.  The host enqueues check_every iterations, then reads
+// the flag (one 4-byte copy and a stream synchronisation) to decide whether
+// to enqueue more; a final guarded copy moves an even-count result to out.
+skel_status run_image_while(skel_plan p, const skel_buffer* args, hipStream_t s) {
+    const Linear& L = p->lin;
+    const int nargs = (int)p->proto.size();
+    uint32_t* hist = L.red == SKEL_RED_HIST256_SUM ? (uint32_t*)args[2].data : nullptr;
+    uint64_t* sum = L.red == SKEL_RED_HIST256_SUM ? (uint64_t*)args[3].data : (uint64_t*)args[2].data;
+    uint32_t* count = (uint32_t*)args[nargs - 1].data;
+    WhileCond wc;
+    memset(&wc, 0, sizeof(wc));
+    wc.channel = L.wcond.channel;
+    wc.cmp = L.wcond.cmp;
+    wc.threshold = L.wcond.threshold;
+    wc.max = L.while_max;
+    const int every = L.wcond.check_every > 0 ? L.wcond.check_every : 8;
+    HIP_TRY(launch_while_init(p->wstate, s));
+    int it = 0;
+    while (it < L.while_max) {
+        for (int j = 0; j < every && it < L.while_max; ++j, ++it) {
+            void* src = it == 0 ? args[0].data : (it % 2 == 1 ? args[1].data : p->wbuf);
+            void* dst = it % 2 == 0 ? args[1].data : p->wbuf;
+            for (size_t ki = 0; ki < p->kernels.size(); ++ki) {
+                Kernel& k = p->kernels[ki];
+                ImgGroupArgs A = k.img;
+                A.in = (const uint8_t*)(k.src == -1 ? src : (k.src == -2 ? dst : p->scratch[k.src]));
+                A.out = (uint8_t*)(k.dst == -2 ? dst : (k.dst >= 0 ? p->scratch[k.dst] : nullptr));
+                A.guard = p->wstate;
+                if (k.reduce) {
+                    A.part = p->hrows;
+                    A.hist = hist;
+                    A.sum = sum;
+                }
+                HIP_TRY(launch_img_group(A, k.blur, k.reduce, k.wg, p->cfg.variant, s, &k.name));
+                if (k.reduce) {
+                    HistFinArgs F;
+                    memset(&F, 0, sizeof(F));
+                    F.part = p->hrows;
+                    F.guard = p->wstate;
+                    F.one.hist = hist;
+                    F.one.sum = sum;
+                    F.one.nrows = k.grid;
+                    F.one.crows = hist_chunk_rows(k.bins);
+                    F.nseg = 1;
+                    F.nchunks = hist_chunks(k.grid, F.one.crows);
+                    F.bins = k.bins;
+                    HIP_TRY(A.ntiles > 0 ? launch_hist_merge(F, s) : launch_hist_zero(F, s));
+                }
+            }
+            HIP_TRY(launch_while_step(p->wstate, sum, wc, count, s));
+        }
+        if (it < L.while_max) {
+            HIP_TRY(hipMemcpyAsync(p->h_flag, p->wstate, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+            HIP_TRY(hipStreamSynchronize(s));
+            if (*p->h_flag == 0) break;
+        }
+    }
+    HIP_TRY(launch_while_copy(p->wstate, p->wbuf, args[1].data, (uint64_t)p->sh.W * p->sh.H * 4, s));
     return SKEL_OK;
 }
 
@@ -272,6 +344,11 @@ skel_status ensure_resources(skel_plan p) {
                 HIP_TRY(hipMalloc(&p->hrows, sizeof(uint32_t) * words * rows));
             }
     }
+    if (p->lin.dom == DOM_U8 && p->lin.is_while && !p->wstate) {
+        HIP_TRY(hipMalloc(&p->wbuf, std::max<size_t>(bytes, 16)));
+        HIP_TRY(hipMalloc(&p->wstate, 256));
+        HIP_TRY(hipHostMalloc((void**)&p->h_flag, 256, hipHostMallocDefault));
+    }
     if (p->lin.dom == DOM_NBODY && p->cfg.fusion == SKEL_FUSE_OFF && !p->nb_acc)
         HIP_TRY(hipMalloc(&p->nb_acc, sizeof(float4) * std::max<int64_t>(p->sh.N, 1)));
     p->resources_ready = true;
@@ -359,6 +436,27 @@ skel_status skel_loop(skel_node body, const skel_loop_state* ls, skel_node* out)
     return SKEL_OK;
 }
 
+skel_status skel_loop_while(skel_node body, const skel_loop_state* ls, const skel_loop_cond* cond,
+                            skel_node* out) {
+    clear_error();
+    if (!body || !ls || !cond) return set_error(SKEL_EINVAL, "null loop body, state or condition");
+    if (ls->iterations < 1) return set_error(SKEL_EINVAL, "a while Loop needs an iteration limit >= 1");
+    if (body->kind != NK_MAPRED) return set_error(SKEL_EINVAL, "a while Loop's body must be a MapReduce");
+    if (cond->channel < 0 || cond->channel > 3) return set_error(SKEL_EINVAL, "condition channel must be 0..3");
+    if (cond->cmp < SKEL_CMP_GT || cond->cmp > SKEL_CMP_LE) return set_error(SKEL_EINVAL, "unknown comparison");
+    if (cond->check_every < 0) return set_error(SKEL_EINVAL, "negative check interval");
+    skel_node_s* n;
+    skel_status st = new_node(out, &n);
+    if (st) return st;
+    n->kind = NK_WHILE;
+    n->loop = *ls;
+    n->cond = *cond;
+    node_addref(body);
+    n->kids.push_back(body);
+    *out = n;
+    return SKEL_OK;
+}
+
 skel_status skel_node_release(skel_node node) {
     clear_error();
     node_release(node);
@@ -404,7 +502,7 @@ skel_status skel_plan_run(skel_plan p, const skel_buffer* args, int32_t nargs, v
     if ((st = ensure_resources(p))) return st;
     const hipStream_t s = S(stream);
     switch (p->lin.dom) {
-        case DOM_U8: return run_image(p, args, s);
+        case DOM_U8: return p->lin.is_while ? run_image_while(p, args, s) : run_image(p, args, s);
         case DOM_F32: return run_vector(p, args, s);
         case DOM_NBODY: return run_nbody(p, args, s);
         default: return set_error(SKEL_EINVAL, "plan has no domain");
@@ -431,9 +529,18 @@ skel_status skel_plan_describe(skel_plan p, char* buf, size_t len) {
     s += "],\"reduce\":";
     s += p->lin.red < 0 ? "null" : (p->lin.red == SKEL_RED_HIST256_SUM ? "\"hist256_sum\"" : "\"sum\"");
     char tmp[256];
-    snprintf(tmp, sizeof(tmp), ",\"iterations\":%d,\"loop_carried\":%u,\"loop_sync\":%d,\"kernels\":[",
+    snprintf(tmp, sizeof(tmp), ",\"iterations\":%d,\"loop_carried\":%u,\"loop_sync\":%d",
              p->lin.nbody_iters, p->lin.loop_carried, p->lin.loop_sync);
     s += tmp;
+    if (p->lin.is_while)
+        snprintf(tmp, sizeof(tmp),
+                 ",\"while\":{\"max\":%d,\"channel\":%d,\"cmp\":%d,\"threshold\":%llu,\"check_every\":%d}",
+                 p->lin.while_max, p->lin.wcond.channel, p->lin.wcond.cmp,
+                 (unsigned long long)p->lin.wcond.threshold, p->lin.wcond.check_every);
+    else
+        snprintf(tmp, sizeof(tmp), ",\"while\":null");
+    s += tmp;
+    s += ",\"kernels\":[";
     for (size_t i = 0; i < p->kernels.size(); ++i) {
         const Kernel& k = p->kernels[i];
         snprintf(tmp, sizeof(tmp),
@@ -473,6 +580,9 @@ skel_status skel_plan_destroy(skel_plan p) {
         if (q) hipFree(q);
     if (p->partials) hipFree(p->partials);
     if (p->hrows) hipFree(p->hrows);
+    if (p->wbuf) hipFree(p->wbuf);
+    if (p->wstate) hipFree(p->wstate);
+    if (p->h_flag) hipHostFree(p->h_flag);
     if (p->d_segs) hipFree(p->d_segs);
     if (p->h_segs) hipHostFree(p->h_segs);
     if (p->b_rows) hipFree(p->b_rows);

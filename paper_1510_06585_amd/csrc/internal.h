@@ -13,7 +13,7 @@
 namespace skel {
 
 enum Domain { DOM_NONE = 0, DOM_U8 = 1, DOM_F32 = 2, DOM_NBODY = 3 };
-enum NodeKind { NK_MAP = 0, NK_PIPE = 1, NK_MAPRED = 2, NK_LOOP = 3 };
+enum NodeKind { NK_MAP = 0, NK_PIPE = 1, NK_MAPRED = 2, NK_LOOP = 3, NK_WHILE = 4 };
 
 constexpr int kMaxStages = 4096;       // linearised Map stages after unrolling loops
 constexpr int kMaxNBodyIters = 4096;   // N-body loop iterations captured in one graph
@@ -33,6 +33,7 @@ struct skel_node_s {
     std::vector<skel_node_s*> kids;
     int red = -1;
     skel_loop_state loop{};
+    skel_loop_cond cond{};
 };
 
 namespace skel {
@@ -54,6 +55,9 @@ struct Linear {
     uint32_t loop_carried = 0;
     int loop_sync = 0;
     uint32_t seen_ops = 0;        // bit op: stage kind present in the tree (also in 0-trip loops)
+    bool is_while = false;        // root is a while Loop over an image MapReduce (st = one iteration)
+    int while_max = 0;
+    skel_loop_cond wcond{};
     std::string sct;              // textual form of the tree
 };
 
@@ -120,6 +124,9 @@ struct skel_plan_s {
     void* scratch[2] = {nullptr, nullptr};
     float* partials = nullptr;
     uint32_t* hrows = nullptr;      // image reduce: histogram rows, one per work-group
+    void* wbuf = nullptr;           // while Loop: second image of the iteration ping-pong
+    uint32_t* wstate = nullptr;     // while Loop: device {continue flag, iterations run}
+    uint32_t* h_flag = nullptr;     // while Loop: pinned host copy of the flag
     float4* nb_acc = nullptr;
     // N-body loop graph
     hipStream_t cap_stream = nullptr;

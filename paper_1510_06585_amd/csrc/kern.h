@@ -40,6 +40,7 @@ struct ImgGroupArgs {
     int32_t in_flip, out_flip;
     int32_t write_out;   // 0 for a reduce-only kernel
     int32_t hist_ks;     // log2 of the histogram copies per bin (see hist_copies_log2)
+    const uint32_t* guard;   // while Loop: the launch does nothing when *guard == 0 (null: always runs)
     OpList pre, post;
 };
 
@@ -83,6 +84,7 @@ struct HistSeg {
 };
 struct HistFinArgs {
     const uint32_t* part;
+    const uint32_t* guard;   // as ImgGroupArgs::guard
     const HistSeg* segs;   // device array of nseg segments, or null for `one`
     HistSeg one;
     int32_t nseg;
@@ -96,6 +98,21 @@ int hist_chunk_rows(int bins);
 inline int hist_chunks(int n, int crows) { return n > 0 ? (n + crows - 1) / crows : 0; }
 hipError_t launch_hist_merge(const HistFinArgs& a, hipStream_t s);
 hipError_t launch_hist_zero(const HistFinArgs& a, hipStream_t s);
+
+// While Loop on the device.  state[0] = 1 while the loop runs, state[1] =
+// iterations run.  init sets {1, 0}; step (after each iteration's merge) counts
+// the iteration, stores the count to *count_out and clears the flag when
+// count == max or the condition on sum[channel] fails; copy moves `bytes`
+// from src to dst when the count is even (the last iteration wrote src).
+struct WhileCond {
+    int32_t channel, cmp;
+    uint64_t threshold;
+    int32_t max, pad;
+};
+hipError_t launch_while_init(uint32_t* state, hipStream_t s);
+hipError_t launch_while_step(uint32_t* state, const uint64_t* sum, const WhileCond& c, uint32_t* count_out,
+                             hipStream_t s);
+hipError_t launch_while_copy(const uint32_t* state, const void* src, void* dst, uint64_t bytes, hipStream_t s);
 
 // Work list entry of the batched persistent kernel (one per request).
 struct BatchReq {

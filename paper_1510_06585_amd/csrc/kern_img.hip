@@ -19,6 +19,7 @@
 #include "kern_common.h"
 #include "kern.h"
 
+#include <algorithm>
 #include <type_traits>
 
 namespace skel {
@@ -460,6 +461,7 @@ static __device__ __forceinline__ void write_hist_row(const uint32_t* lh, int hk
 template <int PRE, int POST, bool BLUR, bool HIST, int FL>
 __global__ void __launch_bounds__(256) img_band_kernel(const ImgGroupArgs A) {
     __shared__ uint32_t lh[HIST ? 4 * kHistWgChan : 1];
+    if (A.guard && *A.guard == 0) return;   // a finished while Loop: the whole grid returns
     const int lane = threadIdx.x & 63;
     const int nw = blockDim.x >> 6;
     const int wave = wave_uniform(threadIdx.x >> 6);
@@ -586,6 +588,7 @@ static __device__ __forceinline__ u32x4 sum_rows(const uint32_t* base, int nrows
 __global__ void __launch_bounds__(kFinThreads) hist_merge_kernel(const HistFinArgs F) {
     __shared__ u32x4 red[kFinThreads];
     __shared__ unsigned long long csum[4];
+    if (F.guard && *F.guard == 0) return;
     const int k = blockIdx.x;
     const HistSeg& S = F.segs ? F.segs[seg_of(F, k)] : F.one;
     const int words = 4 * F.bins;
@@ -629,10 +632,46 @@ __global__ void __launch_bounds__(kFinThreads) hist_merge_kernel(const HistFinAr
 
 // Clears the histogram and sums of every segment (one work-group each).
 __global__ void hist_zero_kernel(const HistFinArgs F) {
+    if (F.guard && *F.guard == 0) return;
     const HistSeg& S = F.segs ? F.segs[blockIdx.x] : F.one;
     for (int b = threadIdx.x; b < 1024; b += blockDim.x)
         if (S.hist) S.hist[b] = 0;
     if (threadIdx.x < 4 && S.sum) S.sum[threadIdx.x] = 0;
+}
+
+__global__ void while_init_kernel(uint32_t* st) {
+    if (threadIdx.x == 0) {
+        st[0] = 1u;
+        st[1] = 0u;
+    }
+}
+
+__global__ void while_step_kernel(uint32_t* st, const uint64_t* sum, const WhileCond c, uint32_t* count_out) {
+    if (threadIdx.x != 0 || st[0] == 0u) return;
+    const uint32_t n = st[1] + 1u;
+    st[1] = n;
+    *count_out = n;
+    const uint64_t v = sum[c.channel];
+    bool go;
+    switch (c.cmp) {
+        case 0: go = v > c.threshold; break;
+        case 1: go = v >= c.threshold; break;
+        case 2: go = v < c.threshold; break;
+        default: go = v <= c.threshold; break;
+    }
+    if (!go || n >= (uint32_t)c.max) st[0] = 0u;
+}
+
+// Copies src to dst (nvec 16-byte vectors, then 4-byte words up to `words`)
+// when the number of iterations run is even.
+__global__ void while_copy_kernel(const uint32_t* st, const uint32_t* src, uint32_t* dst, uint64_t words,
+                                  uint64_t nvec) {
+    if (st[1] % 2u != 0u) return;
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nvec; i += stride)
+        reinterpret_cast<u32x4*>(dst)[i] = reinterpret_cast<const u32x4*>(src)[i];
+    for (uint64_t i = nvec * 4 + (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < words; i += stride)
+        dst[i] = src[i];
 }
 
 __global__ void fill_u32_kernel(uint32_t* p, uint64_t n, uint32_t v) {
@@ -777,6 +816,31 @@ int img_batch_blocks_per_cu(const BatchArgs& a, int wg) {
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, reinterpret_cast<const void*>(e->bfn), wg, 0) != hipSuccess)
         return 0;
     return nb;
+}
+
+hipError_t launch_while_init(uint32_t* state, hipStream_t s) {
+    hipLaunchKernelGGL(while_init_kernel, dim3(1), dim3(64), 0, s, state);
+    return hipGetLastError();
+}
+
+hipError_t launch_while_step(uint32_t* state, const uint64_t* sum, const WhileCond& c, uint32_t* count_out,
+                             hipStream_t s) {
+    if (c.channel < 0 || c.channel > 3) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(while_step_kernel, dim3(1), dim3(64), 0, s, state, sum, c, count_out);
+    return hipGetLastError();
+}
+
+hipError_t launch_while_copy(const uint32_t* state, const void* src, void* dst, uint64_t bytes, hipStream_t s) {
+    if (bytes == 0) return hipSuccess;
+    if (bytes % 4) return hipErrorInvalidValue;
+    const uint64_t words = bytes / 4;
+    const bool aligned = (((uintptr_t)src | (uintptr_t)dst) & 15u) == 0;
+    const uint64_t nvec = aligned ? words / 4 : 0;
+    uint64_t blocks = ((aligned ? nvec : words) + 255) / 256;
+    blocks = std::max<uint64_t>(1, std::min<uint64_t>(blocks, 8192));
+    hipLaunchKernelGGL(while_copy_kernel, dim3((unsigned)blocks), dim3(256), 0, s, state, (const uint32_t*)src,
+                       (uint32_t*)dst, words, nvec);
+    return hipGetLastError();
 }
 
 hipError_t launch_fill_u32(void* p, uint64_t nwords, uint32_t value, hipStream_t s) {

@@ -92,6 +92,24 @@ static skel_status lin_rec(const skel_node_s* n, Linear& L, bool root, int depth
             L.sct += ")";
             return SKEL_OK;
         }
+        case NK_WHILE: {
+            if (!root) return set_error(SKEL_EINVAL, "a while Loop is only valid at the root of a plan");
+            if (n->kids.empty() || !n->kids[0] || n->kids[0]->kind != NK_MAPRED)
+                return set_error(SKEL_EINVAL, "a while Loop's body must be a MapReduce");
+            char buf[64];
+            snprintf(buf, sizeof(buf), "while[%d;ch%d;cmp%d;%llu](", n->loop.iterations, n->cond.channel,
+                     n->cond.cmp, (unsigned long long)n->cond.threshold);
+            L.sct += buf;
+            skel_status st = lin_rec(n->kids[0], L, true, depth + 1);
+            if (st) return st;
+            L.sct += ")";
+            L.is_while = true;
+            L.while_max = n->loop.iterations;
+            L.wcond = n->cond;
+            L.loop_carried |= n->loop.carried_mask;
+            L.loop_sync |= n->loop.global_sync;
+            return SKEL_OK;
+        }
         case NK_MAPRED: {
             if (!root) return set_error(SKEL_EINVAL, "MapReduce is only valid at the root of a plan");
             L.sct += "mapreduce(";
@@ -137,6 +155,8 @@ skel_status linearize(skel_node root, Linear& L) {
     }
     if (img && vec) return set_error(SKEL_ETYPE, "image stages and fp32 vector stages cannot share a chain");
     L.dom = img ? DOM_U8 : (vec ? DOM_F32 : DOM_NONE);
+    if (L.is_while && L.dom == DOM_F32)
+        return set_error(SKEL_ETYPE, "a while Loop's body must be an image MapReduce (exact integer condition)");
     if (L.dom == DOM_F32 && L.red == SKEL_RED_HIST256_SUM)
         return set_error(SKEL_ETYPE, "the histogram reduce applies to RGBA uint8 images only");
     int k = 0;
@@ -147,7 +167,8 @@ skel_status linearize(skel_node root, Linear& L) {
 
 int expected_nargs(const Linear& L) {
     if (L.dom == DOM_NBODY) return 3;
-    if (L.dom == DOM_U8) return 2 + (L.red == SKEL_RED_HIST256_SUM ? 2 : (L.red == SKEL_RED_SUM ? 1 : 0));
+    if (L.dom == DOM_U8)
+        return 2 + (L.red == SKEL_RED_HIST256_SUM ? 2 : (L.red == SKEL_RED_SUM ? 1 : 0)) + (L.is_while ? 1 : 0);
     if (L.dom == DOM_F32) {
         int ns = 0;
         for (const Stage& s : L.st) ns += s.op == SKEL_OP_SAXPY;
@@ -206,6 +227,10 @@ skel_status derive_shape(const Linear& L, const skel_buffer* proto, int32_t narg
         } else if (L.red == SKEL_RED_SUM) {
             const int64_t ss[1] = {4};
             if ((st = check_buf(proto[2], 2, SKEL_U64, 1, ss))) return st;
+        }
+        if (L.is_while) {
+            const int64_t one[1] = {1};
+            if ((st = check_buf(proto[nargs - 1], nargs - 1, SKEL_U32, 1, one))) return st;
         }
         if (W > kMaxDim || H > kMaxDim)
             return set_error(SKEL_EUNSUPPORTED, "image sides are limited to %d pixels", kMaxDim);

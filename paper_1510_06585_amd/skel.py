@@ -22,6 +22,8 @@ OP_NOISE, OP_SOLARISE, OP_MIRROR, OP_BLUR5, OP_SAXPY, OP_NBODY_FORCE, OP_LEAPFRO
 RED_HIST256_SUM, RED_SUM = 0, 1
 FUSE_AUTO, FUSE_OFF, FUSE_ON, FUSE_MASK = -1, 0, 1, 2
 IMMUTABLE, COPY = 1, 2
+CMP_GT, CMP_GE, CMP_LT, CMP_LE = range(4)
+CMP_BY_NAME = {">": CMP_GT, ">=": CMP_GE, "<": CMP_LT, "<=": CMP_LE}
 
 OP_BY_NAME = {"noise": OP_NOISE, "solarise": OP_SOLARISE, "mirror": OP_MIRROR, "blur5": OP_BLUR5,
               "saxpy": OP_SAXPY, "nbody_force": OP_NBODY_FORCE, "leapfrog": OP_LEAPFROG}
@@ -51,6 +53,11 @@ class LoopState(ctypes.Structure):
                 ("global_sync", ctypes.c_int32)]
 
 
+class LoopCond(ctypes.Structure):
+    _fields_ = [("channel", ctypes.c_int32), ("cmp", ctypes.c_int32), ("threshold", ctypes.c_uint64),
+                ("check_every", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
 class PlanOpts(ctypes.Structure):
     _fields_ = [("fusion", ctypes.c_int32), ("split_mask", ctypes.c_uint32), ("tile_w", ctypes.c_int32),
                 ("tile_h", ctypes.c_int32), ("wg", ctypes.c_int32), ("ept", ctypes.c_int32),
@@ -72,6 +79,8 @@ _SIGS = {
     "skel_pipeline": (ctypes.c_int32, [ctypes.POINTER(_node_p), ctypes.c_int32, ctypes.POINTER(_node_p)]),
     "skel_mapreduce": (ctypes.c_int32, [_node_p, ctypes.c_int32, ctypes.POINTER(_node_p)]),
     "skel_loop": (ctypes.c_int32, [_node_p, ctypes.POINTER(LoopState), ctypes.POINTER(_node_p)]),
+    "skel_loop_while": (ctypes.c_int32, [_node_p, ctypes.POINTER(LoopState), ctypes.POINTER(LoopCond),
+                                         ctypes.POINTER(_node_p)]),
     "skel_node_release": (ctypes.c_int32, [_node_p]),
     "skel_plan_compile": (ctypes.c_int32, [_node_p, ctypes.POINTER(Buffer), ctypes.c_int32,
                                            ctypes.POINTER(PlanOpts), ctypes.POINTER(_vp)]),
@@ -243,6 +252,18 @@ def Loop(body: Node, iterations: int, carried_mask: int = 0, global_sync: int = 
     st = LoopState(iterations, carried_mask, global_sync)
     h = _node_p()
     _check(lib().skel_loop(body.handle, ctypes.byref(st), ctypes.byref(h)))
+    return Node(h.value)
+
+
+def LoopWhile(body: Node, max_iterations: int, channel: int, cmp, threshold: int, check_every: int = 0,
+              carried_mask: int = 0, global_sync: int = 0) -> Node:
+    """While Loop over an image MapReduce body: repeat while sum[channel] <cmp>
+    threshold (cmp: CMP_* or one of ">", ">=", "<", "<="), at most
+    max_iterations times; the condition is evaluated on the device."""
+    st = LoopState(max_iterations, carried_mask, global_sync)
+    c = LoopCond(channel, CMP_BY_NAME.get(cmp, cmp), threshold, check_every, 0)
+    h = _node_p()
+    _check(lib().skel_loop_while(body.handle, ctypes.byref(st), ctypes.byref(c), ctypes.byref(h)))
     return Node(h.value)
 
 

@@ -181,3 +181,36 @@ def test_pipeline_order_is_stage_order(orc):
 def test_image_rows_generator_matches_full_draw():
     a = synth.image(7, 37, 53)
     assert (synth.image_rows(7, 37, 53, 5, 20) == a[5:20]).all()
+
+
+# ------------------------------------------------------------- while Loop
+def test_while_loop_counts_on_constant_image(orc):
+    """A 5x5 box blur leaves a constant image unchanged, so the channel sums stay
+    W*H*v: a condition that holds runs the body to the limit, one that fails
+    stops after the first iteration (the body runs at least once)."""
+    img = np.full((6, 9, 4), 40, np.uint8)
+    body = [("blur5", {})]
+    total = 6 * 9 * 40
+    out, h, s, n = orc.run_image_while(img, body, "hist_sum", 2, ">", total - 1, 7)
+    assert n == 7 and (out == img).all() and int(s[2]) == total and int(h[2, 40]) == 54
+    out, h, s, n = orc.run_image_while(img, body, "hist_sum", 2, "<", total, 7)
+    assert n == 1
+    _, _, _, n = orc.run_image_while(img, body, "sum", 0, ">=", total, 1)
+    assert n == 1
+
+
+def test_while_loop_matches_library_iteration(orc):
+    """The loop against an explicit iteration of scipy's 'nearest' correlation
+    with a 5x5 box followed by one floor division (the blur's definition)."""
+    from scipy.ndimage import correlate
+    img = np.random.default_rng(8).integers(0, 256, (23, 31, 4), dtype=np.uint8)
+    seq, cur = [], img.astype(np.int64)
+    for _ in range(8):
+        cur = np.stack([correlate(cur[..., c], np.ones((5, 5), np.int64), mode="nearest") // 25
+                        for c in range(4)], axis=-1)
+        seq.append((cur.copy(), cur.reshape(-1, 4).sum(0)))
+    T = int(seq[4][1][1])
+    stop = next(i for i, (_, s) in enumerate(seq) if int(s[1]) <= T) + 1
+    out, h, s, n = orc.run_image_while(img, [("blur5", {})], "hist_sum", 1, ">", T, 8)
+    assert n == stop
+    assert (out.astype(np.int64) == seq[stop - 1][0]).all() and (s.astype(np.int64) == seq[stop - 1][1]).all()
