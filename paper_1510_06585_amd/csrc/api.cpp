@@ -168,12 +168,13 @@ skel_status run_image(skel_plan p, const skel_buffer* args, hipStream_t s) {
 }
 
 // While Loop (skel_loop_while): iteration i (from 0) reads the previous
-// iteration's image (the input for i = 0) and writes out when i is even, the
-// plan's second image otherwise; every kernel of an iteration is guarded by
-// the device flag, which the step kernel clears when the condition fails or
-// the limit is reached.  The host enqueues check_every iterations, then reads
-// the flag (one 4-byte copy and a stream synchronisation) to decide whether
-// to enqueue more; a final guarded copy moves an even-count result to out.
+// iteration's image (the input for i = 0) and writes out when max - 1 - i is
+// even, the plan's second image otherwise, so a loop that runs to its limit
+// ends in out; every kernel of an iteration is guarded by the device flag,
+// which the step kernel clears when the condition fails or the limit is
+// reached.  The host enqueues check_every iterations, then reads the flag
+// (one 4-byte copy and a stream synchronisation) to decide whether to enqueue
+// more; a final guarded copy moves a result that ended in the second image.
 skel_status run_image_while(skel_plan p, const skel_buffer* args, hipStream_t s) {
     const Linear& L = p->lin;
     const int nargs = (int)p->proto.size();
@@ -191,8 +192,9 @@ skel_status run_image_while(skel_plan p, const skel_buffer* args, hipStream_t s)
     int it = 0;
     while (it < L.while_max) {
         for (int j = 0; j < every && it < L.while_max; ++j, ++it) {
-            void* src = it == 0 ? args[0].data : (it % 2 == 1 ? args[1].data : p->wbuf);
-            void* dst = it % 2 == 0 ? args[1].data : p->wbuf;
+            auto dst_of = [&](int i) { return (L.while_max - 1 - i) % 2 == 0 ? args[1].data : p->wbuf; };
+            void* src = it == 0 ? args[0].data : dst_of(it - 1);
+            void* dst = dst_of(it);
             for (size_t ki = 0; ki < p->kernels.size(); ++ki) {
                 Kernel& k = p->kernels[ki];
                 ImgGroupArgs A = k.img;
@@ -228,7 +230,8 @@ skel_status run_image_while(skel_plan p, const skel_buffer* args, hipStream_t s)
             if (*p->h_flag == 0) break;
         }
     }
-    HIP_TRY(launch_while_copy(p->wstate, p->wbuf, args[1].data, (uint64_t)p->sh.W * p->sh.H * 4, s));
+    HIP_TRY(launch_while_copy(p->wstate, p->wbuf, args[1].data, (uint64_t)p->sh.W * p->sh.H * 4,
+                              (uint32_t)L.while_max, s));
     return SKEL_OK;
 }
 

@@ -103,7 +103,7 @@ hipError_t launch_hist_zero(const HistFinArgs& a, hipStream_t s);
 // iterations run.  init sets {1, 0}; step (after each iteration's merge) counts
 // the iteration, stores the count to *count_out and clears the flag when
 // count == max or the condition on sum[channel] fails; copy moves `bytes`
-// from src to dst when the count is even (the last iteration wrote src).
+// from src to dst when max - count is odd (the last iteration wrote src).
 struct WhileCond {
     int32_t channel, cmp;
     uint64_t threshold;
@@ -112,7 +112,8 @@ struct WhileCond {
 hipError_t launch_while_init(uint32_t* state, hipStream_t s);
 hipError_t launch_while_step(uint32_t* state, const uint64_t* sum, const WhileCond& c, uint32_t* count_out,
                              hipStream_t s);
-hipError_t launch_while_copy(const uint32_t* state, const void* src, void* dst, uint64_t bytes, hipStream_t s);
+hipError_t launch_while_copy(const uint32_t* state, const void* src, void* dst, uint64_t bytes, uint32_t max,
+                             hipStream_t s);
 
 // Work list entry of the batched persistent kernel (one per request).
 struct BatchReq {

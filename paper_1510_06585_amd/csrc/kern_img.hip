@@ -663,10 +663,10 @@ __global__ void while_step_kernel(uint32_t* st, const uint64_t* sum, const While
 }
 
 // Copies src to dst (nvec 16-byte vectors, then 4-byte words up to `words`)
-// when the number of iterations run is even.
+// when max - (iterations run) is odd: the last iteration then wrote src.
 __global__ void while_copy_kernel(const uint32_t* st, const uint32_t* src, uint32_t* dst, uint64_t words,
-                                  uint64_t nvec) {
-    if (st[1] % 2u != 0u) return;
+                                  uint64_t nvec, uint32_t max) {
+    if ((max - st[1]) % 2u == 0u) return;
     const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
     for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nvec; i += stride)
         reinterpret_cast<u32x4*>(dst)[i] = reinterpret_cast<const u32x4*>(src)[i];
@@ -830,7 +830,8 @@ hipError_t launch_while_step(uint32_t* state, const uint64_t* sum, const WhileCo
     return hipGetLastError();
 }
 
-hipError_t launch_while_copy(const uint32_t* state, const void* src, void* dst, uint64_t bytes, hipStream_t s) {
+hipError_t launch_while_copy(const uint32_t* state, const void* src, void* dst, uint64_t bytes, uint32_t max,
+                             hipStream_t s) {
     if (bytes == 0) return hipSuccess;
     if (bytes % 4) return hipErrorInvalidValue;
     const uint64_t words = bytes / 4;
@@ -839,7 +840,7 @@ hipError_t launch_while_copy(const uint32_t* state, const void* src, void* dst, 
     uint64_t blocks = ((aligned ? nvec : words) + 255) / 256;
     blocks = std::max<uint64_t>(1, std::min<uint64_t>(blocks, 8192));
     hipLaunchKernelGGL(while_copy_kernel, dim3((unsigned)blocks), dim3(256), 0, s, state, (const uint32_t*)src,
-                       (uint32_t*)dst, words, nvec);
+                       (uint32_t*)dst, words, nvec, max);
     return hipGetLastError();
 }
 
