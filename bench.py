@@ -263,7 +263,7 @@ def bench_batch():
     root = sk.image_chain(CFG2, "hist_sum")
     proto = [sk.proto([8, 8, 4], sk.U8)] * 2 + [sk.proto([4, 256], sk.U32), sk.proto([4], sk.U64)]
     res = {"requests": 256, "pixels": px}
-    bp = sk.Plan(root, proto, {"tile_h": 64})
+    bp = sk.Plan(root, proto)
     _, ms = timed_runs(lambda: bp.batch_run(reqs), 10, 2)
     ms /= 10
     res["batched_ms"] = round(ms, 4)

@@ -81,7 +81,14 @@ extern "C" skel_status skel_batch_run(skel_plan p, const skel_buffer* args, int3
     }
     if (nreq == 0) return SKEL_OK;
     const hipStream_t s = (hipStream_t)stream;
-    const int tile_h = p->cfg.tile_h;
+    // Rows per tile: the plan's tile_h when it was given, else per request
+    // ceil(H / 32) within [32, 128]: tall tiles (little halo recompute) for
+    // the large requests that run first, short ones for the small requests
+    // that form the tail of the work list.
+    auto tile_rows = [&](int64_t H) -> int {
+        if (!p->cfg.auto_tile) return p->cfg.tile_h;
+        return (int)std::min<int64_t>(128, std::max<int64_t>(32, (H + 31) / 32));
+    };
     const int bw = K.blur ? kBandOut : kBandPx;
 
     std::vector<int64_t> key;
@@ -139,7 +146,8 @@ extern "C" skel_status skel_batch_run(skel_plan p, const skel_buffer* args, int3
         R.H = (int32_t)a[0].shape[0];
         R.W = (int32_t)a[0].shape[1];
         R.nbands = (R.W + bw - 1) / bw;
-        R.nchunks = (R.H + tile_h - 1) / tile_h;
+        R.tile_h = tile_rows(R.H);
+        R.nchunks = (R.H + R.tile_h - 1) / R.tile_h;
         R.tile_begin = (int32_t)tiles;
         const int64_t nt = (R.W > 0 && R.H > 0) ? (int64_t)R.nbands * R.nchunks : 0;
         tiles += nt;
@@ -186,7 +194,6 @@ extern "C" skel_status skel_batch_run(skel_plan p, const skel_buffer* args, int3
     A.tile_req = p->d_tile_req;
     A.nreq = nreq;
     A.ntiles = (int32_t)tiles;
-    A.tile_h = tile_h;
     A.has_blur = K.blur;
     A.in_flip = K.img.in_flip;
     A.out_flip = K.img.out_flip;

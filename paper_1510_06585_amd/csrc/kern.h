@@ -124,14 +124,13 @@ struct BatchReq {
     int32_t W, H;
     int32_t nbands, nchunks;
     int32_t tile_begin;  // first global tile index of this request
-    int32_t pad;
+    int32_t tile_h;      // rows per tile of this request
 };
 struct BatchArgs {
     const BatchReq* reqs;
     const uint16_t* tile_req;   // request index of every tile
     int32_t nreq;
     int32_t ntiles;
-    int32_t tile_h;
     int32_t has_blur;
     int32_t in_flip, out_flip;
     int32_t has_hist;

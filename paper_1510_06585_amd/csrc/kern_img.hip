@@ -513,8 +513,8 @@ __global__ void __launch_bounds__(256) img_batch_kernel(const BatchArgs A) {
         const int lt = (int)t - R.tile_begin;
         const int band = lt % R.nbands;
         const int chunk = lt / R.nbands;
-        const int y0 = chunk * A.tile_h;
-        const int y1 = min(y0 + A.tile_h, R.H);
+        const int y0 = chunk * R.tile_h;
+        const int y1 = min(y0 + R.tile_h, R.H);
         if constexpr (HIST) {
             for (int b = lane; b < 4 * kHistWaveChan; b += 64) lh[b] = 0;
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
