@@ -332,6 +332,36 @@ def bench_while():
     return res
 
 
+def bench_fft():
+    """FFT pipelined with its inversion (the paper's FFT benchmark) over 512
+    transforms of 65536 complex fp32 points (256 MiB): fused (3 passes) vs one
+    kernel per half-stage (4 passes)."""
+    import torch
+    import paper_1510_06585_amd as sk
+    import synth
+    B = 512
+    x = torch.from_numpy(synth.complex_batch(synth.SEED_FFT, B)).cuda()
+    y = torch.empty_like(x)
+    root = sk.image_chain([("fft", {}), ("ifft", {})])
+    elems = B * 65536
+    algo = 2.0 * elems * 8                      # read the input once, write the output once
+    res = {"transforms": B, "points": 65536}
+    for name, opt in (("fused", {}), ("plain", {"fusion": sk.FUSE_OFF})):
+        p = sk.Plan(root, [x, y], opt)
+        b = sk.bind([x, y])
+        _, ms = timed_runs(lambda: p.run(b), 20, 5)
+        ms /= 20
+        passes = len(p.describe()["kernels"])
+        res[f"{name}_ms"] = round(ms, 4)
+        res[f"{name}_passes"] = passes
+        res[f"{name}_gelem_s"] = round(elems / (ms * 1e-3) / 1e9, 2)
+        res[f"{name}_pass_traffic_gbs"] = round(passes * algo / (ms * 1e-3) / 1e9, 1)
+        p.destroy()
+    res["fused_vs_plain_speedup"] = round(res["plain_ms"] / res["fused_ms"], 3)
+    res["fused_hbm_frac_of_pass_traffic"] = round(res["fused_pass_traffic_gbs"] / HBM_PEAK_GBS, 4)
+    return res
+
+
 def profile_run(steps):
     """Short run for hardware-counter passes: the fused config-2 kernel and a
     plain copy of the same image (the byte-count reference), `steps` each."""
@@ -396,6 +426,8 @@ def main():
         extras["batched_256"] = bench_batch()
         log("while Loop: device-evaluated condition, 8192x8192 x 10")
         extras["while_loop_8192x10"] = bench_while()
+        log("FFT pipelined with its inverse: 512 x 65536 complex fp32")
+        extras["fft_pipeline_512x65536"] = bench_fft()
         out["extras"] = extras
     if not a.no_cpu_baseline:
         log("cpu baseline: oracle on the host")

@@ -86,6 +86,10 @@ typedef struct skel_buffer {
  *            a_i = G sum_j m_j (r_j - r_i) (|r_j - r_i|^2 + eps^2)^(-3/2), then
  *            kick-drift v += dt a, r += dt v.  Only valid as
  *            Pipeline(NBODY_FORCE, LEAPFROG), optionally inside a Loop.
+ *  FFT, IFFT (Sec. 4 FFT, pipelined with its inversion) per transform of
+ *            65536 complex fp32 points (512 KiB): X[k] = sum_n x[n] w^(nk),
+ *            w = exp(-2 pi i / 65536) (FFT) or exp(+2 pi i / 65536) with a
+ *            1/65536 factor (IFFT).  Only FFT / IFFT stages may share a chain.
  */
 enum {
     SKEL_OP_NOISE = 0,
@@ -94,7 +98,9 @@ enum {
     SKEL_OP_BLUR5 = 3,
     SKEL_OP_SAXPY = 4,
     SKEL_OP_NBODY_FORCE = 5,
-    SKEL_OP_LEAPFROG = 6
+    SKEL_OP_LEAPFROG = 6,
+    SKEL_OP_FFT = 7,
+    SKEL_OP_IFFT = 8
 };
 
 /* Reduce side of MapReduce (Sec. 2.1; partial results merged by addition,
@@ -238,6 +244,11 @@ skel_status skel_node_release(skel_node node);
  *                 [, sum f32 [1]]                     (SUM)
  *  N-body         pos f32 [N,4] (x,y,z,m), vel f32 [N,4] (w unused),
  *                 pos_scratch f32 [N,4]; after a run the positions are in pos.
+ *  FFT chains     in f32 [B,65536,2], out f32 [B,65536,2] (B transforms,
+ *                 interleaved re, im; in and out must not overlap).  A fused
+ *                 chain of L stages runs L + 1 kernels (the second half of
+ *                 a stage and the first half of the next share one), an
+ *                 unfused one 2L; split_mask bits split between stages.
  * opts may be NULL (defaults).  Compilation is host-only: the plan's device
  * scratch (intermediate images between unfused kernels, partial sums, graph
  * state) is allocated on the current device by its first run.  Errors:

@@ -182,6 +182,25 @@ def run_image_while(img: np.ndarray, stages, reduce: str, channel: int, cmp: str
             return cur, hist, s, count
 
 
+# ------------------------------------------------------------------ FFT stages
+def fft_chain(x: np.ndarray, stages):
+    """Pipeline of FFT / IFFT stages (Sec. 4 FFT, pipelined with its inversion)
+    over the last axis of ``x`` (float32 [..., N, 2] as interleaved re, im),
+    each stage materialised in complex128 with numpy's FFT (the library FFT is
+    the step; the forward transform uses exp(-2 pi i nk / N), the inverse
+    exp(+2 pi i nk / N) / N).  Returns complex128 [..., N]."""
+    x = np.asarray(x)
+    cur = x[..., 0].astype(np.float64) + 1j * x[..., 1].astype(np.float64)
+    for name in stages:
+        if name == "fft":
+            cur = np.fft.fft(cur, axis=-1)
+        elif name == "ifft":
+            cur = np.fft.ifft(cur, axis=-1)
+        else:
+            raise ValueError(name)
+    return cur
+
+
 # ------------------------------------------------------------------ fp32 stages
 def _f32(a: np.ndarray) -> np.ndarray:
     a = np.ascontiguousarray(a)

@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cmath>
 #include <cstdio>
 #include <cstring>
 #include <new>
@@ -117,6 +118,8 @@ skel_status check_aliasing(skel_plan p, const skel_buffer* args) {
             }
             return set_error(SKEL_EINVAL, "argument %d overlaps the output", k);
         }
+    } else if (L.dom == DOM_C32) {
+        if (overlap(args[0], args[1])) return set_error(SKEL_EINVAL, "FFT input and output must not overlap");
     } else if (L.dom == DOM_NBODY) {
         for (int a = 0; a < 3; ++a)
             for (int b = a + 1; b < 3; ++b)
@@ -235,6 +238,27 @@ skel_status run_image_while(skel_plan p, const skel_buffer* args, hipStream_t s)
     return SKEL_OK;
 }
 
+skel_status run_fft(skel_plan p, const skel_buffer* args, hipStream_t s) {
+    for (size_t ki = 0; ki < p->kernels.size(); ++ki) {
+        Kernel& k = p->kernels[ki];
+        FftArgs A = k.fft;
+        auto res = [&](int id) -> void* {
+            if (id == -1) return args[0].data;
+            if (id == -2) return args[1].data;
+            return p->scratch[id];
+        };
+        A.in = res(k.src);
+        A.out = res(k.dst);
+        A.tw = p->fft_tw;
+        A.nfft = (int32_t)p->sh.n;
+        const bool prof = (int)ki == p->prof_kernel;
+        if (prof) HIP_TRY(hipEventRecord(p->prof_start, s));
+        HIP_TRY(launch_fft_pass(A, k.fft_mode, s));
+        if (prof) HIP_TRY(hipEventRecord(p->prof_end, s));
+    }
+    return SKEL_OK;
+}
+
 skel_status run_vector(skel_plan p, const skel_buffer* args, hipStream_t s) {
     const Linear& L = p->lin;
     const int nargs = (int)p->proto.size();
@@ -331,6 +355,7 @@ skel_status ensure_resources(skel_plan p) {
     size_t bytes = 0;
     if (p->lin.dom == DOM_U8) bytes = (size_t)(p->sh.W * p->sh.H * 4);
     if (p->lin.dom == DOM_F32) bytes = (size_t)(p->sh.n * 4);
+    if (p->lin.dom == DOM_C32) bytes = (size_t)p->sh.n * kFftPoints * 8;
     for (int k = 0; k < nscr; ++k)
         if (!p->scratch[k]) HIP_TRY(hipMalloc(&p->scratch[k], std::max<size_t>(bytes, 16)));
     if (p->lin.dom == DOM_F32 && p->lin.red >= 0 && !p->partials) {
@@ -346,6 +371,16 @@ skel_status ensure_resources(skel_plan p) {
                 const size_t rows = std::max(1, k.grid);
                 HIP_TRY(hipMalloc(&p->hrows, sizeof(uint32_t) * words * rows));
             }
+    }
+    if (p->lin.dom == DOM_C32 && !p->fft_tw) {
+        // Roots of unity (cos, sin)(2 pi m / N) in double precision, rounded once.
+        std::vector<float2> tw(kFftPoints);
+        for (int m = 0; m < kFftPoints; ++m) {
+            const double a = 2.0 * 3.14159265358979323846 * (double)m / (double)kFftPoints;
+            tw[m] = make_float2((float)std::cos(a), (float)std::sin(a));
+        }
+        HIP_TRY(hipMalloc(&p->fft_tw, sizeof(float2) * kFftPoints));
+        HIP_TRY(hipMemcpy(p->fft_tw, tw.data(), sizeof(float2) * kFftPoints, hipMemcpyHostToDevice));
     }
     if (p->lin.dom == DOM_U8 && p->lin.is_while && !p->wstate) {
         HIP_TRY(hipMalloc(&p->wbuf, std::max<size_t>(bytes, 16)));
@@ -379,7 +414,7 @@ skel_status skel_init(int32_t device) {
 
 skel_status skel_map(int32_t op, const skel_params* p, skel_node* out) {
     clear_error();
-    if (op < SKEL_OP_NOISE || op > SKEL_OP_LEAPFROG) return set_error(SKEL_EINVAL, "unknown stage op %d", op);
+    if (op < SKEL_OP_NOISE || op > SKEL_OP_IFFT) return set_error(SKEL_EINVAL, "unknown stage op %d", op);
     skel_node_s* n;
     skel_status st = new_node(out, &n);
     if (st) return st;
@@ -508,6 +543,7 @@ skel_status skel_plan_run(skel_plan p, const skel_buffer* args, int32_t nargs, v
         case DOM_U8: return p->lin.is_while ? run_image_while(p, args, s) : run_image(p, args, s);
         case DOM_F32: return run_vector(p, args, s);
         case DOM_NBODY: return run_nbody(p, args, s);
+        case DOM_C32: return run_fft(p, args, s);
         default: return set_error(SKEL_EINVAL, "plan has no domain");
     }
 }
@@ -523,10 +559,11 @@ skel_status skel_plan_describe(skel_plan p, char* buf, size_t len) {
     clear_error();
     if (!p || !buf || len == 0) return set_error(SKEL_EINVAL, "null plan or buffer");
     std::string s = "{\"sct\":\"" + p->lin.sct + "\",\"domain\":\"";
-    s += p->lin.dom == DOM_U8 ? "u8" : (p->lin.dom == DOM_F32 ? "f32" : "nbody");
+    s += p->lin.dom == DOM_U8 ? "u8" : (p->lin.dom == DOM_F32 ? "f32" : (p->lin.dom == DOM_C32 ? "c32" : "nbody"));
     s += "\",\"stages\":[";
     for (size_t i = 0; i < p->lin.st.size(); ++i) {
-        static const char* nm[] = {"noise", "solarise", "mirror", "blur5", "saxpy", "nbody_force", "leapfrog"};
+        static const char* nm[] = {"noise", "solarise", "mirror", "blur5", "saxpy", "nbody_force", "leapfrog",
+                                   "fft", "ifft"};
         s += (i ? ",\"" : "\"") + std::string(nm[p->lin.st[i].op]) + "\"";
     }
     s += "],\"reduce\":";
@@ -582,6 +619,7 @@ skel_status skel_plan_destroy(skel_plan p) {
     for (void* q : p->scratch)
         if (q) hipFree(q);
     if (p->partials) hipFree(p->partials);
+    if (p->fft_tw) hipFree(p->fft_tw);
     if (p->hrows) hipFree(p->hrows);
     if (p->wbuf) hipFree(p->wbuf);
     if (p->wstate) hipFree(p->wstate);

@@ -12,7 +12,7 @@
 
 namespace skel {
 
-enum Domain { DOM_NONE = 0, DOM_U8 = 1, DOM_F32 = 2, DOM_NBODY = 3 };
+enum Domain { DOM_NONE = 0, DOM_U8 = 1, DOM_F32 = 2, DOM_NBODY = 3, DOM_C32 = 4 };
 enum NodeKind { NK_MAP = 0, NK_PIPE = 1, NK_MAPRED = 2, NK_LOOP = 3, NK_WHILE = 4 };
 
 constexpr int kMaxStages = 4096;       // linearised Map stages after unrolling loops
@@ -93,6 +93,8 @@ struct Kernel {
     int dst = 0;               // -2 user output, 0/1 scratch, -3 none
     ImgGroupArgs img{};        // image kernels (pointers filled per run)
     VecGroupArgs vec{};        // vector kernels
+    FftArgs fft{};             // FFT passes (pointers filled per run)
+    int fft_mode = 0;          // 0 pass A, 1 fused B+A, 2 pass B
     std::vector<int> side_args;
     int grid = 0, wg = 0;
     int bins = 256;            // exclusive bound of the values this kernel emits
@@ -123,6 +125,7 @@ struct skel_plan_s {
     // plan-owned device memory (allocated on the first run)
     void* scratch[2] = {nullptr, nullptr};
     float* partials = nullptr;
+    float2* fft_tw = nullptr;       // FFT roots of unity
     uint32_t* hrows = nullptr;      // image reduce: histogram rows, one per work-group
     void* wbuf = nullptr;           // while Loop: second image of the iteration ping-pong
     uint32_t* wstate = nullptr;     // while Loop: device {continue flag, iterations run}

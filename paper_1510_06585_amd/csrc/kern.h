@@ -169,6 +169,23 @@ struct VecGroupArgs {
 // the work-group partials into a.sum_out.
 hipError_t launch_vec_group(const VecGroupArgs& a, int grid, int wg, hipStream_t s, const char** kname);
 
+// --------------------------------------------------------------- complex FFT
+// Batched 65536-point complex fp32 transforms (interleaved re, im), four-step
+// 256 x 256.  mode 0: pass A (natural order in, transposed out), mode 1:
+// pass B of a stage fused with pass A of the next, mode 2: pass B
+// (transposed in, natural order out).  in and out must not overlap.
+struct FftArgs {
+    const void* in;
+    void* out;
+    const float2* tw;    // 65536 roots of unity (cos, sin)(2 pi m / 65536)
+    int32_t nfft;        // transforms in the batch
+    int32_t dir1, dir2;  // -1 forward, +1 inverse
+    float scale1;        // applied to a stage's pass-B result (1/65536 after an inverse)
+};
+constexpr int kFftPoints = 65536;
+hipError_t launch_fft_pass(const FftArgs& a, int mode, hipStream_t s);
+const char* fft_pass_name(int mode);
+
 // -------------------------------------------------------------------- N-body
 struct NBodyArgs {
     const float4* pos_in;   // [N] x,y,z,m

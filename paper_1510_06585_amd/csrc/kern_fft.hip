@@ -1,0 +1,207 @@
+// gfx950 kernels for batched complex fp32 FFT chains (the paper's FFT
+// benchmark: FFTs of 512 KiB, i.e. 65536 complex fp32 points, pipelined
+// with their inverses, Sec. 4).
+//
+// A 65536-point transform is computed as 256 x 256 (four-step): with
+// n = n1 + 256 n2 and k = k2 + 256 k1,
+//   pass A:  for every n1, a 256-point DFT over n2 -> k2, times W_N^(n1 k2),
+//            stored transposed as T[k2][n1];
+//   pass B:  for every k2, a 256-point DFT over n1 -> k1, giving X[k2 + 256 k1].
+// Pass B of one stage and pass A of the next work on the same index (the
+// next stage's n1 is this stage's k2), so a fused chain of L stages runs
+// L + 1 kernels (A, L - 1 fused "BA", B) instead of 2L: the data between
+// two stages never goes back to HBM.
+//
+// One work-group (512 threads) owns 32 columns or rows of one transform: it
+// loads a 32 x 256 tile (each row of 32 elements is one 256-byte run), does
+// the 256-point DFTs in LDS as 16 x 16 (a 16-point DFT per thread, a twiddle
+// by W_256, a second 16-point DFT), and stores the tile the same way.
+// Twiddles W_N^m are products of two roots from 256-entry LDS tables taken
+// from the 65536 roots of unity computed in double precision on the host.
+#include "kern_common.h"
+#include "kern.h"
+
+namespace skel {
+
+constexpr int kFftN = kFftPoints;
+constexpr int kFftR = 256;     // row / column length
+constexpr int kFftCols = 32;   // rows or columns per work-group (256-byte runs)
+constexpr int kFftThreads = 16 * kFftCols;   // 16 threads per 256-point DFT
+// LDS tile layout: element m of row j at j * kRowStride + m + m / 16.  The
+// pad after every 16 elements and the odd row stride keep both the in-row
+// stride-16 reads of the DFT and the down-a-column accesses of the loads and
+// stores free of bank conflicts (8-byte elements span 2 of the 32 banks).
+constexpr int kRowStride = kFftR + kFftR / 16 + 1;
+static __device__ __forceinline__ int sx(int j, int m) { return j * kRowStride + m + (m >> 4); }
+
+struct cpx {
+    float x, y;
+};
+static __device__ __forceinline__ cpx cadd(cpx a, cpx b) { return {a.x + b.x, a.y + b.y}; }
+static __device__ __forceinline__ cpx csub(cpx a, cpx b) { return {a.x - b.x, a.y - b.y}; }
+static __device__ __forceinline__ cpx cmul(cpx a, cpx b) {
+    return {__builtin_fmaf(a.x, b.x, -a.y * b.y), __builtin_fmaf(a.x, b.y, a.y * b.x)};
+}
+// a * (dir * i): dir = -1 forward, +1 inverse.
+static __device__ __forceinline__ cpx cmul_i(cpx a, int dir) { return dir < 0 ? cpx{a.y, -a.x} : cpx{-a.y, a.x}; }
+
+// Roots of unity in LDS: TH[h] = W^(256 h) and TL[l] = W^l (h, l < 256,
+// W = exp(2 pi i / N)), so W^m = TH[m >> 8] TL[m & 255] from two reads
+// instead of a scattered read of a 512 KiB table.
+struct TwLds {
+    cpx hi[256], lo[256];
+};
+
+static __device__ __forceinline__ void load_tw(TwLds& L, const float2* T) {
+    for (int i = threadIdx.x; i < 256; i += blockDim.x) {
+        const float2 h = T[256 * i], l = T[i];
+        L.hi[i] = {h.x, h.y};
+        L.lo[i] = {l.x, l.y};
+    }
+}
+
+// W_N^m in direction dir: (cos, dir * sin)(2 pi m / N), m taken mod N.
+static __device__ __forceinline__ cpx tw(const TwLds& L, uint32_t m, int dir) {
+    m &= (uint32_t)(kFftN - 1);
+    cpx w = L.hi[m >> 8];
+    if (m & 255u) w = cmul(w, L.lo[m & 255u]);
+    return {w.x, dir < 0 ? -w.y : w.y};
+}
+
+// In-register 4-point DFT of (a, b, c, d) in direction dir.
+static __device__ __forceinline__ void dft4(cpx& a, cpx& b, cpx& c, cpx& d, int dir) {
+    const cpx s0 = cadd(a, c), d0 = csub(a, c), s1 = cadd(b, d), d1 = cmul_i(csub(b, d), dir);
+    a = cadd(s0, s1);
+    c = csub(s0, s1);
+    b = cadd(d0, d1);
+    d = csub(d0, d1);
+}
+
+// In-register 16-point DFT, v[c] -> v[k] in natural order, as 4 x 4:
+// c = c1 + 4 c2, k = k2 + 4 k1; a 4-point DFT over c2, the twiddle
+// W_16^(c1 k2), a 4-point DFT over c1.
+static __device__ __forceinline__ void dft16(cpx (&v)[16], const TwLds& T, int dir) {
+#pragma unroll
+    for (int c1 = 0; c1 < 4; ++c1) dft4(v[c1], v[c1 + 4], v[c1 + 8], v[c1 + 12], dir);
+    // v[c1 + 4 k2] now holds U[c1][k2]
+#pragma unroll
+    for (int c1 = 1; c1 < 4; ++c1)
+#pragma unroll
+        for (int k2 = 1; k2 < 4; ++k2) v[c1 + 4 * k2] = cmul(v[c1 + 4 * k2], tw(T, (uint32_t)(c1 * k2) * (kFftN / 16), dir));
+    cpx o[16];
+#pragma unroll
+    for (int k2 = 0; k2 < 4; ++k2) {
+        cpx a = v[0 + 4 * k2], b = v[1 + 4 * k2], c = v[2 + 4 * k2], d = v[3 + 4 * k2];
+        dft4(a, b, c, d, dir);
+        o[k2] = a;
+        o[k2 + 4] = b;
+        o[k2 + 8] = c;
+        o[k2 + 12] = d;
+    }
+#pragma unroll
+    for (int k = 0; k < 16; ++k) v[k] = o[k];
+}
+
+// 256-point DFTs of the kFftCols rows of S (S[j][m], m = 0..255) in direction
+// dir, in place, natural order; thread t works on row t / 16.  Ends
+// synchronised.
+static __device__ __forceinline__ void dft256_rows(cpx* S, const TwLds& T, int dir) {
+    const int j = threadIdx.x >> 4, u = threadIdx.x & 15;
+    cpx v[16];
+    // m = a + 16 c with a = u: 16-point DFT over c, twiddle W_256^(a p).
+#pragma unroll
+    for (int c = 0; c < 16; ++c) v[c] = S[sx(j, u + 16 * c)];
+    dft16(v, T, dir);
+#pragma unroll
+    for (int p = 1; p < 16; ++p) v[p] = cmul(v[p], tw(T, (uint32_t)(u * p) * (kFftN / kFftR), dir));
+    __syncthreads();
+#pragma unroll
+    for (int p = 0; p < 16; ++p) S[sx(j, 16 * p + u)] = v[p];   // Z[a = u][p] at 16 p + a
+    __syncthreads();
+    // for p = u: 16-point DFT over a -> k = p + 16 q
+#pragma unroll
+    for (int a = 0; a < 16; ++a) v[a] = S[sx(j, 16 * u + a)];
+    dft16(v, T, dir);
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < 16; ++q) S[sx(j, u + 16 * q)] = v[q];
+    __syncthreads();
+}
+
+// MODE 0 (A): in natural order -> T layout; MODE 1 (BA): T -> T (pass B of
+// one stage, pass A of the next); MODE 2 (B): T -> natural order.  dir1 is
+// the direction of the first DFT, dir2 of the second (MODE 1); scale1 (1/N
+// after an inverse stage, else 1) multiplies the result of a stage's pass B.
+template <int MODE>
+__global__ void __launch_bounds__(kFftThreads) fft_pass_kernel(const FftArgs A) {
+    __shared__ cpx S[kFftCols * kRowStride];
+    __shared__ TwLds W;
+    load_tw(W, A.tw);
+    const int b = blockIdx.x / (kFftR / kFftCols);
+    const int g = blockIdx.x % (kFftR / kFftCols);
+    const int t = threadIdx.x;
+    const cpx* in = reinterpret_cast<const cpx*>(A.in) + (size_t)b * kFftN;
+    cpx* out = reinterpret_cast<cpx*>(A.out) + (size_t)b * kFftN;
+    // load: element (j, m) of the tile into S[j][m]
+    if (MODE == 0) {
+        // column n1 = kFftCols g + j, rows n2 = m: x[n1 + 256 m]
+#pragma unroll
+        for (int i = 0; i < 16; ++i) {
+            const int e = t + kFftThreads * i, j = e % kFftCols, m = e / kFftCols;
+            S[sx(j, m)] = in[kFftCols * g + j + kFftR * m];
+        }
+    } else {
+        // row k2 = kFftCols g + j of T: T[k2][m] at k2 * 256 + m
+#pragma unroll
+        for (int i = 0; i < 16; ++i) {
+            const int e = t + kFftThreads * i, j = e / kFftR, m = e % kFftR;
+            S[sx(j, m)] = in[(kFftCols * g + j) * kFftR + m];
+        }
+    }
+    __syncthreads();
+    dft256_rows(S, W, A.dir1);
+    if (MODE == 1) {
+        // S[j][k1] = X[k2 + 256 k1] of the first stage (k2 = kFftCols g + j): it
+        // is the second stage's input at n1' = k2, n2' = k1.
+        if (A.scale1 != 1.0f)
+            for (int e = t; e < kFftCols * kRowStride; e += kFftThreads) S[e] = {S[e].x * A.scale1, S[e].y * A.scale1};
+        __syncthreads();
+        dft256_rows(S, W, A.dir2);
+    }
+    if (MODE == 0 || MODE == 1) {
+        // twiddle W_N^(n1 k2) (n1 = kFftCols g + j, k2 = m) and store T[k2][n1]
+        const int dir = MODE == 0 ? A.dir1 : A.dir2;
+#pragma unroll
+        for (int i = 0; i < 16; ++i) {
+            const int e = t + kFftThreads * i, j = e % kFftCols, m = e / kFftCols;
+            const cpx w = tw(W, (uint32_t)(kFftCols * g + j) * (uint32_t)m, dir);
+            out[m * kFftR + kFftCols * g + j] = cmul(S[sx(j, m)], w);
+        }
+    } else {
+        // X[k2 + 256 k1] with k2 = kFftCols g + j, k1 = m
+#pragma unroll
+        for (int i = 0; i < 16; ++i) {
+            const int e = t + kFftThreads * i, j = e % kFftCols, m = e / kFftCols;
+            const cpx v = S[sx(j, m)];
+            out[kFftCols * g + j + kFftR * m] = {v.x * A.scale1, v.y * A.scale1};
+        }
+    }
+}
+
+hipError_t launch_fft_pass(const FftArgs& a, int mode, hipStream_t s) {
+    if (a.nfft <= 0) return hipSuccess;
+    const dim3 grid((unsigned)(a.nfft * (kFftR / kFftCols)));
+    switch (mode) {
+        case 0: hipLaunchKernelGGL(fft_pass_kernel<0>, grid, dim3(kFftThreads), 0, s, a); break;
+        case 1: hipLaunchKernelGGL(fft_pass_kernel<1>, grid, dim3(kFftThreads), 0, s, a); break;
+        case 2: hipLaunchKernelGGL(fft_pass_kernel<2>, grid, dim3(kFftThreads), 0, s, a); break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+const char* fft_pass_name(int mode) {
+    return mode == 0 ? "fft_pass_a" : (mode == 1 ? "fft_pass_ba" : "fft_pass_b");
+}
+
+}  // namespace skel

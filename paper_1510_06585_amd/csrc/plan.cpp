@@ -42,6 +42,8 @@ static const char* op_name(int op) {
         case SKEL_OP_SAXPY: return "saxpy";
         case SKEL_OP_NBODY_FORCE: return "nbody_force";
         case SKEL_OP_LEAPFROG: return "leapfrog";
+        case SKEL_OP_FFT: return "fft";
+        case SKEL_OP_IFFT: return "ifft";
     }
     return "?";
 }
@@ -131,6 +133,15 @@ skel_status linearize(skel_node root, Linear& L) {
     const int img = has(SKEL_OP_NOISE) + has(SKEL_OP_SOLARISE) + has(SKEL_OP_BLUR5);
     const int vec = has(SKEL_OP_SAXPY);
     const int nb = has(SKEL_OP_NBODY_FORCE) + has(SKEL_OP_LEAPFROG);
+    const int ff = has(SKEL_OP_FFT) + has(SKEL_OP_IFFT);
+    if (ff) {
+        if (img || vec || nb || has(SKEL_OP_MIRROR))
+            return set_error(SKEL_ETYPE, "FFT / IFFT stages cannot share a chain with other stages");
+        if (L.red >= 0) return set_error(SKEL_ETYPE, "FFT chains have no reduce side");
+        if (L.is_while) return set_error(SKEL_ETYPE, "a while Loop's body must be an image MapReduce");
+        L.dom = DOM_C32;
+        return SKEL_OK;
+    }
     if (nb) {
         if (img || vec || has(SKEL_OP_MIRROR) || L.red >= 0 || (L.st.size() % 2) != 0)
             return set_error(SKEL_ETYPE, "N-body stages must form Pipeline(nbody_force, leapfrog), optionally looped");
@@ -167,6 +178,7 @@ skel_status linearize(skel_node root, Linear& L) {
 
 int expected_nargs(const Linear& L) {
     if (L.dom == DOM_NBODY) return 3;
+    if (L.dom == DOM_C32) return 2;
     if (L.dom == DOM_U8)
         return 2 + (L.red == SKEL_RED_HIST256_SUM ? 2 : (L.red == SKEL_RED_SUM ? 1 : 0)) + (L.is_while ? 1 : 0);
     if (L.dom == DOM_F32) {
@@ -239,6 +251,15 @@ skel_status derive_shape(const Linear& L, const skel_buffer* proto, int32_t narg
         sh.H = H;
         return SKEL_OK;
     }
+    if (L.dom == DOM_C32) {
+        const int64_t B = proto[0].shape[0];
+        const int64_t fs[3] = {B, kFftPoints, 2};
+        if ((st = check_buf(proto[0], 0, SKEL_F32, 3, fs))) return st;
+        if ((st = check_buf(proto[1], 1, SKEL_F32, 3, fs))) return st;
+        if (B > 65535) return set_error(SKEL_EUNSUPPORTED, "at most 65535 transforms per run");
+        sh.n = B;
+        return SKEL_OK;
+    }
     if (L.dom == DOM_F32) {
         const int64_t n = proto[0].shape[0];
         const int64_t vs[1] = {n};
@@ -304,6 +325,11 @@ skel_status resolve_config(const Linear& L, const Shape& sh, const skel_plan_opt
         c.ept = o->ept ? o->ept : (nvec >= ((int64_t)1 << 20) ? 4 : 1);
         if (c.ept < 1 || c.ept > 64) return set_error(SKEL_EINVAL, "ept out of range");
         c.tile_h = 0;
+    } else if (L.dom == DOM_C32) {
+        c.wg = 256;
+        if (o->wg && o->wg != 256) return set_error(SKEL_EINVAL, "FFT passes take wg 256");
+        c.tile_h = 0;
+        c.ept = 1;
     } else if (L.dom == DOM_NBODY) {
         c.tile_h = o->tile_h ? o->tile_h : 4;
         if (c.tile_h < 1 || c.tile_h > 16) return set_error(SKEL_EINVAL, "N-body j-slices must be 1..16");
@@ -445,6 +471,47 @@ skel_status build_kernels(const Linear& L, const Shape& sh, const Config& c, std
             g.first = 1;
             g.name = "nbody_kick_drift";
             ks.push_back(g);
+        }
+        return SKEL_OK;
+    }
+    if (L.dom == DOM_C32) {
+        // Stage i splits from stage i + 1 when unfused or split_mask bit i is
+        // set: its pass B then writes natural order and the next stage starts
+        // with a pass A; otherwise the two share one fused B+A kernel.
+        const int k = (int)L.st.size();
+        auto dir = [&](int i) { return L.st[i].op == SKEL_OP_IFFT ? 1 : -1; };
+        auto split = [&](int i) {
+            return c.fusion == SKEL_FUSE_OFF || (c.fusion == SKEL_FUSE_MASK && ((c.split_mask >> i) & 1u));
+        };
+        auto add = [&](int mode, int i, int first, int last) {
+            Kernel K;
+            K.first = first;
+            K.last = last;
+            K.wg = 512;
+            K.grid = (int)(sh.n * 8);
+            K.fft_mode = mode;
+            memset(&K.fft, 0, sizeof(K.fft));
+            K.fft.dir1 = dir(i);
+            K.fft.dir2 = mode == 1 ? dir(i + 1) : 0;
+            K.fft.scale1 = (mode != 0 && L.st[i].op == SKEL_OP_IFFT) ? 1.0f / (float)kFftPoints : 1.0f;
+            K.name = fft_pass_name(mode);
+            ks.push_back(K);
+        };
+        add(0, 0, 0, 1);
+        for (int i = 0; i < k; ++i) {
+            if (i == k - 1) {
+                add(2, i, i, i + 1);
+            } else if (split(i)) {
+                add(2, i, i, i + 1);
+                add(0, i + 1, i + 1, i + 2);
+            } else {
+                add(1, i, i, i + 2);
+            }
+        }
+        const int nk = (int)ks.size();
+        for (int g = 0; g < nk; ++g) {
+            ks[g].src = g == 0 ? -1 : ((g - 1) % 2);
+            ks[g].dst = g == nk - 1 ? -2 : (g % 2);
         }
         return SKEL_OK;
     }

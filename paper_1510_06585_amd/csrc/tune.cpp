@@ -52,7 +52,12 @@ std::vector<Config> enumerate_configs(const Linear& L, const Shape& sh) {
     else
         masks.push_back(0);
     for (uint32_t m : masks) {
-        if (L.dom == DOM_U8) {
+        if (L.dom == DOM_C32) {
+            Config c = base;
+            c.fusion = k >= 1 ? SKEL_FUSE_MASK : SKEL_FUSE_ON;
+            c.split_mask = m;
+            if (config_valid(L, sh, c)) out.push_back(c);
+        } else if (L.dom == DOM_U8) {
             const int th0 = base.tile_h;
             const int variants[3][2] = {{256, th0}, {64, std::max(8, th0 / 2)}, {256, std::min(1024, th0 * 2)}};
             for (const auto& v : variants) {
@@ -96,7 +101,10 @@ void features(const Linear& L, const Shape& sh, const Config& c, float* f) {
     for (int i = 0; i < 6; ++i) f[i] = (float)cnt[i];
     const int k = (int)L.st.size();
     f[6] = (float)k;
-    const double n = L.dom == DOM_U8 ? (double)sh.W * sh.H : (L.dom == DOM_F32 ? (double)sh.n : (double)sh.N);
+    const double n = L.dom == DOM_U8    ? (double)sh.W * sh.H
+                     : L.dom == DOM_F32 ? (double)sh.n
+                     : L.dom == DOM_C32 ? (double)sh.n * kFftPoints
+                                        : (double)sh.N;
     f[7] = (float)lg2(n);
     f[8] = L.dom == DOM_U8 ? 1.0f : 0.0f;
     f[9] = (float)cnt[4];   // side-vector streams of an fp32 chain
@@ -123,6 +131,7 @@ void features(const Linear& L, const Shape& sh, const Config& c, float* f) {
         if (L.dom == DOM_U8) bytes += (K.dst == -3 ? 1.0 : 2.0) * n * 4.0;
         if (L.dom == DOM_F32) bytes += ((K.dst == -3 ? 1.0 : 2.0) + K.side_args.size()) * n * 4.0;
         if (L.dom == DOM_NBODY) bytes += 48.0 * n;
+        if (L.dom == DOM_C32) bytes += 16.0 * n;
     }
     f[20] = (float)worst;
     f[21] = red_fused ? 1.0f : 0.0f;

@@ -18,7 +18,8 @@ LIB_PATH = os.path.join(_HERE, "libskel.so")
 # --------------------------------------------------------------- constants
 OK, EINVAL, ESHAPE, ETYPE, ENOMEM, EDEVICE, EUNSUPPORTED = range(7)
 U8, U32, U64, F32, F64 = range(5)
-OP_NOISE, OP_SOLARISE, OP_MIRROR, OP_BLUR5, OP_SAXPY, OP_NBODY_FORCE, OP_LEAPFROG = range(7)
+OP_NOISE, OP_SOLARISE, OP_MIRROR, OP_BLUR5, OP_SAXPY, OP_NBODY_FORCE, OP_LEAPFROG, OP_FFT, OP_IFFT = range(9)
+FFT_POINTS = 65536
 RED_HIST256_SUM, RED_SUM = 0, 1
 FUSE_AUTO, FUSE_OFF, FUSE_ON, FUSE_MASK = -1, 0, 1, 2
 IMMUTABLE, COPY = 1, 2
@@ -26,7 +27,8 @@ CMP_GT, CMP_GE, CMP_LT, CMP_LE = range(4)
 CMP_BY_NAME = {">": CMP_GT, ">=": CMP_GE, "<": CMP_LT, "<=": CMP_LE}
 
 OP_BY_NAME = {"noise": OP_NOISE, "solarise": OP_SOLARISE, "mirror": OP_MIRROR, "blur5": OP_BLUR5,
-              "saxpy": OP_SAXPY, "nbody_force": OP_NBODY_FORCE, "leapfrog": OP_LEAPFROG}
+              "saxpy": OP_SAXPY, "nbody_force": OP_NBODY_FORCE, "leapfrog": OP_LEAPFROG, "fft": OP_FFT,
+              "ifft": OP_IFFT}
 STATUS_NAMES = {OK: "SKEL_OK", EINVAL: "SKEL_EINVAL", ESHAPE: "SKEL_ESHAPE", ETYPE: "SKEL_ETYPE",
                 ENOMEM: "SKEL_ENOMEM", EDEVICE: "SKEL_EDEVICE", EUNSUPPORTED: "SKEL_EUNSUPPORTED"}
 

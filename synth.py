@@ -18,6 +18,7 @@ SEED_PIPE_FUSED = 2        # 8192 x 8192 fused pipeline + MapReduce
 SEED_NBODY = 3             # 65536-body Loop
 SEED_BATCH = 4             # 256 uneven batched requests
 SEED_SELECT = 5            # learned config selector compositions
+SEED_FFT = 6               # batched 65536-point FFT pipeline
 NOISE_SEED = 0x1510
 
 
@@ -39,6 +40,12 @@ def image_rows(seed: int, H: int, W: int, y0: int, y1: int) -> np.ndarray:
             rng.integers(0, 256, k, dtype=np.uint8)
             left -= k
     return rng.integers(0, 256, ((y1 - y0), W, 4), dtype=np.uint8)
+
+
+def complex_batch(seed: int, B: int, N: int = 65536) -> np.ndarray:
+    """B complex fp32 signals of N points as float32 [B, N, 2] (re, im), every
+    component uniform in [-1, 1)."""
+    return np.random.default_rng(seed).uniform(-1.0, 1.0, (B, N, 2)).astype(np.float32)
 
 
 def nbody(seed: int, N: int):
