@@ -362,6 +362,33 @@ def bench_fft():
     return res
 
 
+def bench_segment():
+    """Segmentation (Map over a gray volume, Sec. 4) at the paper's largest
+    size, 60 MiB (240 x 512 x 512 voxels): one stage, and a chain of three
+    stages fused into one pass vs one kernel per stage."""
+    import torch
+    import paper_1510_06585_amd as sk
+    import synth
+    vol = torch.from_numpy(synth.gray_volume(synth.SEED_SEGMENT, 240, 512, 512)).cuda()
+    out = torch.empty_like(vol)
+    n = vol.numel()
+    res = {"voxels": n}
+    for name, stages, opt in (("one_stage", [(0, 0)], {}), ("chain3_fused", [(0, 0), (100, 200), (50, 150)], {}),
+                              ("chain3_plain", [(0, 0), (100, 200), (50, 150)], {"fusion": sk.FUSE_OFF})):
+        p = sk.Plan(sk.image_chain([("segment", {"lo": lo, "hi": hi}) for lo, hi in stages]), [vol, out], opt)
+        b = sk.bind([vol, out])
+        _, ms = timed_runs(lambda: p.run(b), 200, 50)
+        ms /= 200
+        passes = len(p.describe()["kernels"])
+        res[f"{name}_ms"] = round(ms, 4)
+        res[f"{name}_gvox_s"] = round(n / (ms * 1e-3) / 1e9, 1)
+        res[f"{name}_hbm_gbs"] = round(passes * 2.0 * n / (ms * 1e-3) / 1e9, 1)
+        p.destroy()
+    res["one_stage_hbm_frac"] = round(res["one_stage_hbm_gbs"] / HBM_PEAK_GBS, 4)
+    res["chain3_fused_vs_plain_speedup"] = round(res["chain3_plain_ms"] / res["chain3_fused_ms"], 3)
+    return res
+
+
 def profile_run(steps):
     """Short run for hardware-counter passes: the fused config-2 kernel and a
     plain copy of the same image (the byte-count reference), `steps` each."""
@@ -428,6 +455,8 @@ def main():
         extras["while_loop_8192x10"] = bench_while()
         log("FFT pipelined with its inverse: 512 x 65536 complex fp32")
         extras["fft_pipeline_512x65536"] = bench_fft()
+        log("Segmentation: 60 MiB gray volume, one stage and a 3-stage chain")
+        extras["segment_60MiB"] = bench_segment()
         out["extras"] = extras
     if not a.no_cpu_baseline:
         log("cpu baseline: oracle on the host")

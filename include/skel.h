@@ -86,6 +86,10 @@ typedef struct skel_buffer {
  *            a_i = G sum_j m_j (r_j - r_i) (|r_j - r_i|^2 + eps^2)^(-3/2), then
  *            kick-drift v += dt a, r += dt v.  Only valid as
  *            Pipeline(NBODY_FORCE, LEAPFROG), optionally inside a Loop.
+ *  SEGMENT   (Sec. 4 Segmentation) on a gray uint8 volume, every voxel to
+ *            black, gray or white: out = v < lo ? 0 : (v < hi ? 128 : 255),
+ *            lo <= hi <= 256 (both 0: 85 and 170; lo = hi gives no gray,
+ *            hi = 256 no white).  Only SEGMENT stages may share a chain.
  *  FFT, IFFT (Sec. 4 FFT, pipelined with its inversion) per transform of
  *            65536 complex fp32 points (512 KiB): X[k] = sum_n x[n] w^(nk),
  *            w = exp(-2 pi i / 65536) (FFT) or exp(+2 pi i / 65536) with a
@@ -100,7 +104,8 @@ enum {
     SKEL_OP_NBODY_FORCE = 5,
     SKEL_OP_LEAPFROG = 6,
     SKEL_OP_FFT = 7,
-    SKEL_OP_IFFT = 8
+    SKEL_OP_IFFT = 8,
+    SKEL_OP_SEGMENT = 9
 };
 
 /* Reduce side of MapReduce (Sec. 2.1; partial results merged by addition,
@@ -120,6 +125,7 @@ typedef struct skel_params {
     float eps;       /* NBODY_FORCE softening length */
     float G;         /* NBODY_FORCE gravitational constant */
     float dt;        /* LEAPFROG time step */
+    uint32_t lo, hi; /* SEGMENT thresholds (both 0: 85 and 170) */
 } skel_params;
 
 /* Loop state (Sec. 2.1: stop condition, items updated per iteration, whether
@@ -244,6 +250,9 @@ skel_status skel_node_release(skel_node node);
  *                 [, sum f32 [1]]                     (SUM)
  *  N-body         pos f32 [N,4] (x,y,z,m), vel f32 [N,4] (w unused),
  *                 pos_scratch f32 [N,4]; after a run the positions are in pos.
+ *  gray chains    in u8 [D,H,W] (any 1..4-D shape, fewer than 2^31 voxels),
+ *                 out u8 of the same shape; in == out is allowed (voxel-wise
+ *                 stages), any other overlap is rejected
  *  FFT chains     in f32 [B,65536,2], out f32 [B,65536,2] (B transforms,
  *                 interleaved re, im; in and out must not overlap).  A fused
  *                 chain of L stages runs L + 1 kernels (the second half of

@@ -182,6 +182,35 @@ def run_image_while(img: np.ndarray, stages, reduce: str, channel: int, cmp: str
             return cur, hist, s, count
 
 
+# ---------------------------------------------------------- Segmentation stages
+SEGMENT_LO, SEGMENT_HI = 85, 170
+
+
+def segment(vol: np.ndarray, lo: int = SEGMENT_LO, hi: int = SEGMENT_HI) -> np.ndarray:
+    """Segmentation (Sec. 4): every voxel of a gray uint8 volume becomes black
+    (0), gray (128) or white (255).  The paper does not give the thresholds;
+    the reading here: black below ``lo``, white from ``hi`` up, gray between
+    (defaults split 0..255 into three equal ranges of 85 values)."""
+    v = np.asarray(vol)
+    if v.dtype != np.uint8:
+        raise ValueError("volume must be uint8")
+    if not 0 <= lo <= hi <= 256:
+        raise ValueError("need 0 <= lo <= hi <= 256")
+    out = np.full(v.shape, 128, np.uint8)
+    out[v < lo] = 0
+    out[v >= hi] = 255
+    return out
+
+
+def run_segment_chain(vol: np.ndarray, stages) -> np.ndarray:
+    """Pipeline of Segmentation stages, each materialised: stages are
+    (lo, hi) pairs, (0, 0) for the default thresholds."""
+    cur = np.asarray(vol)
+    for lo, hi in stages:
+        cur = segment(cur, lo, hi) if (lo or hi) else segment(cur)
+    return cur
+
+
 # ------------------------------------------------------------------ FFT stages
 def fft_chain(x: np.ndarray, stages):
     """Pipeline of FFT / IFFT stages (Sec. 4 FFT, pipelined with its inversion)

@@ -120,6 +120,9 @@ skel_status check_aliasing(skel_plan p, const skel_buffer* args) {
         }
     } else if (L.dom == DOM_C32) {
         if (overlap(args[0], args[1])) return set_error(SKEL_EINVAL, "FFT input and output must not overlap");
+    } else if (L.dom == DOM_GRAY) {
+        if (overlap(args[0], args[1]) && args[0].data != args[1].data)
+            return set_error(SKEL_EINVAL, "input and output overlap partially");
     } else if (L.dom == DOM_NBODY) {
         for (int a = 0; a < 3; ++a)
             for (int b = a + 1; b < 3; ++b)
@@ -235,6 +238,25 @@ skel_status run_image_while(skel_plan p, const skel_buffer* args, hipStream_t s)
     }
     HIP_TRY(launch_while_copy(p->wstate, p->wbuf, args[1].data, (uint64_t)p->sh.W * p->sh.H * 4,
                               (uint32_t)L.while_max, s));
+    return SKEL_OK;
+}
+
+skel_status run_gray(skel_plan p, const skel_buffer* args, hipStream_t s) {
+    for (size_t ki = 0; ki < p->kernels.size(); ++ki) {
+        Kernel& k = p->kernels[ki];
+        GrayArgs A = k.gray;
+        auto res = [&](int id) -> void* {
+            if (id == -1) return args[0].data;
+            if (id == -2) return args[1].data;
+            return p->scratch[id];
+        };
+        A.in = (const uint8_t*)res(k.src);
+        A.out = (uint8_t*)res(k.dst);
+        const bool prof = (int)ki == p->prof_kernel;
+        if (prof) HIP_TRY(hipEventRecord(p->prof_start, s));
+        HIP_TRY(launch_gray_chain(A, k.grid, k.wg, s));
+        if (prof) HIP_TRY(hipEventRecord(p->prof_end, s));
+    }
     return SKEL_OK;
 }
 
@@ -356,6 +378,7 @@ skel_status ensure_resources(skel_plan p) {
     if (p->lin.dom == DOM_U8) bytes = (size_t)(p->sh.W * p->sh.H * 4);
     if (p->lin.dom == DOM_F32) bytes = (size_t)(p->sh.n * 4);
     if (p->lin.dom == DOM_C32) bytes = (size_t)p->sh.n * kFftPoints * 8;
+    if (p->lin.dom == DOM_GRAY) bytes = (size_t)p->sh.n;
     for (int k = 0; k < nscr; ++k)
         if (!p->scratch[k]) HIP_TRY(hipMalloc(&p->scratch[k], std::max<size_t>(bytes, 16)));
     if (p->lin.dom == DOM_F32 && p->lin.red >= 0 && !p->partials) {
@@ -414,7 +437,9 @@ skel_status skel_init(int32_t device) {
 
 skel_status skel_map(int32_t op, const skel_params* p, skel_node* out) {
     clear_error();
-    if (op < SKEL_OP_NOISE || op > SKEL_OP_IFFT) return set_error(SKEL_EINVAL, "unknown stage op %d", op);
+    if (op < SKEL_OP_NOISE || op > SKEL_OP_SEGMENT) return set_error(SKEL_EINVAL, "unknown stage op %d", op);
+    if (op == SKEL_OP_SEGMENT && p && (p->lo || p->hi) && (p->lo > p->hi || p->hi > 256))
+        return set_error(SKEL_EINVAL, "SEGMENT thresholds need lo <= hi <= 256");
     skel_node_s* n;
     skel_status st = new_node(out, &n);
     if (st) return st;
@@ -544,6 +569,7 @@ skel_status skel_plan_run(skel_plan p, const skel_buffer* args, int32_t nargs, v
         case DOM_F32: return run_vector(p, args, s);
         case DOM_NBODY: return run_nbody(p, args, s);
         case DOM_C32: return run_fft(p, args, s);
+        case DOM_GRAY: return run_gray(p, args, s);
         default: return set_error(SKEL_EINVAL, "plan has no domain");
     }
 }
@@ -559,11 +585,15 @@ skel_status skel_plan_describe(skel_plan p, char* buf, size_t len) {
     clear_error();
     if (!p || !buf || len == 0) return set_error(SKEL_EINVAL, "null plan or buffer");
     std::string s = "{\"sct\":\"" + p->lin.sct + "\",\"domain\":\"";
-    s += p->lin.dom == DOM_U8 ? "u8" : (p->lin.dom == DOM_F32 ? "f32" : (p->lin.dom == DOM_C32 ? "c32" : "nbody"));
+    s += p->lin.dom == DOM_U8    ? "u8"
+         : p->lin.dom == DOM_F32 ? "f32"
+         : p->lin.dom == DOM_C32 ? "c32"
+         : p->lin.dom == DOM_GRAY ? "gray"
+                                  : "nbody";
     s += "\",\"stages\":[";
     for (size_t i = 0; i < p->lin.st.size(); ++i) {
         static const char* nm[] = {"noise", "solarise", "mirror", "blur5", "saxpy", "nbody_force", "leapfrog",
-                                   "fft", "ifft"};
+                                   "fft", "ifft", "segment"};
         s += (i ? ",\"" : "\"") + std::string(nm[p->lin.st[i].op]) + "\"";
     }
     s += "],\"reduce\":";

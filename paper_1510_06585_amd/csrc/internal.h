@@ -12,7 +12,7 @@
 
 namespace skel {
 
-enum Domain { DOM_NONE = 0, DOM_U8 = 1, DOM_F32 = 2, DOM_NBODY = 3, DOM_C32 = 4 };
+enum Domain { DOM_NONE = 0, DOM_U8 = 1, DOM_F32 = 2, DOM_NBODY = 3, DOM_C32 = 4, DOM_GRAY = 5 };
 enum NodeKind { NK_MAP = 0, NK_PIPE = 1, NK_MAPRED = 2, NK_LOOP = 3, NK_WHILE = 4 };
 
 constexpr int kMaxStages = 4096;       // linearised Map stages after unrolling loops
@@ -94,6 +94,7 @@ struct Kernel {
     ImgGroupArgs img{};        // image kernels (pointers filled per run)
     VecGroupArgs vec{};        // vector kernels
     FftArgs fft{};             // FFT passes (pointers filled per run)
+    GrayArgs gray{};           // gray-volume kernels
     int fft_mode = 0;          // 0 pass A, 1 fused B+A, 2 pass B
     std::vector<int> side_args;
     int grid = 0, wg = 0;

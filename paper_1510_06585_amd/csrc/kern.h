@@ -169,6 +169,19 @@ struct VecGroupArgs {
 // the work-group partials into a.sum_out.
 hipError_t launch_vec_group(const VecGroupArgs& a, int grid, int wg, hipStream_t s, const char** kname);
 
+// ------------------------------------------------------------ gray volumes
+// Fused chain of SEGMENT stages over n voxels (bytes): stage k maps v to
+// v < lo[k] ? 0 : (v < hi[k] ? 128 : 255).  in may equal out.
+struct GrayArgs {
+    const uint8_t* in;
+    uint8_t* out;
+    int64_t n;
+    int32_t nops;
+    int32_t ept;          // 16-byte vectors per thread
+    uint16_t lo[kMaxOps], hi[kMaxOps];   // 0 <= lo <= hi <= 256
+};
+hipError_t launch_gray_chain(const GrayArgs& a, int grid, int wg, hipStream_t s);
+
 // --------------------------------------------------------------- complex FFT
 // Batched 65536-point complex fp32 transforms (interleaved re, im), four-step
 // 256 x 256.  mode 0: pass A (natural order in, transposed out), mode 1:

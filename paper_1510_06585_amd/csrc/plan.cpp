@@ -44,6 +44,7 @@ static const char* op_name(int op) {
         case SKEL_OP_LEAPFROG: return "leapfrog";
         case SKEL_OP_FFT: return "fft";
         case SKEL_OP_IFFT: return "ifft";
+        case SKEL_OP_SEGMENT: return "segment";
     }
     return "?";
 }
@@ -134,6 +135,14 @@ skel_status linearize(skel_node root, Linear& L) {
     const int vec = has(SKEL_OP_SAXPY);
     const int nb = has(SKEL_OP_NBODY_FORCE) + has(SKEL_OP_LEAPFROG);
     const int ff = has(SKEL_OP_FFT) + has(SKEL_OP_IFFT);
+    if (has(SKEL_OP_SEGMENT)) {
+        if (img || vec || nb || ff || has(SKEL_OP_MIRROR))
+            return set_error(SKEL_ETYPE, "SEGMENT stages cannot share a chain with other stages");
+        if (L.red >= 0) return set_error(SKEL_ETYPE, "gray-volume chains have no reduce side");
+        if (L.is_while) return set_error(SKEL_ETYPE, "a while Loop's body must be an image MapReduce");
+        L.dom = DOM_GRAY;
+        return SKEL_OK;
+    }
     if (ff) {
         if (img || vec || nb || has(SKEL_OP_MIRROR))
             return set_error(SKEL_ETYPE, "FFT / IFFT stages cannot share a chain with other stages");
@@ -178,7 +187,7 @@ skel_status linearize(skel_node root, Linear& L) {
 
 int expected_nargs(const Linear& L) {
     if (L.dom == DOM_NBODY) return 3;
-    if (L.dom == DOM_C32) return 2;
+    if (L.dom == DOM_C32 || L.dom == DOM_GRAY) return 2;
     if (L.dom == DOM_U8)
         return 2 + (L.red == SKEL_RED_HIST256_SUM ? 2 : (L.red == SKEL_RED_SUM ? 1 : 0)) + (L.is_while ? 1 : 0);
     if (L.dom == DOM_F32) {
@@ -249,6 +258,16 @@ skel_status derive_shape(const Linear& L, const skel_buffer* proto, int32_t narg
         if (W * H * 4 >= ((int64_t)1 << 31)) return set_error(SKEL_EUNSUPPORTED, "images are limited to 2 GiB");
         sh.W = W;
         sh.H = H;
+        return SKEL_OK;
+    }
+    if (L.dom == DOM_GRAY) {
+        if (proto[0].ndim < 1 || proto[0].ndim > 4) return set_error(SKEL_ESHAPE, "argument 0: 1..4 dims");
+        int64_t n = 1;
+        for (int d = 0; d < proto[0].ndim; ++d) n *= proto[0].shape[d];
+        if ((st = check_buf(proto[0], 0, SKEL_U8, proto[0].ndim, proto[0].shape))) return st;
+        if ((st = check_buf(proto[1], 1, SKEL_U8, proto[0].ndim, proto[0].shape))) return st;
+        if (n >= ((int64_t)1 << 31)) return set_error(SKEL_EUNSUPPORTED, "volumes are limited to 2 GiB");
+        sh.n = n;
         return SKEL_OK;
     }
     if (L.dom == DOM_C32) {
@@ -323,6 +342,14 @@ skel_status resolve_config(const Linear& L, const Shape& sh, const skel_plan_opt
         if (c.wg < 64 || c.wg > 1024 || c.wg % 64) return set_error(SKEL_EINVAL, "wg must be a multiple of 64 up to 1024");
         const int64_t nvec = (sh.n + 3) / 4;
         c.ept = o->ept ? o->ept : (nvec >= ((int64_t)1 << 20) ? 4 : 1);
+        if (c.ept < 1 || c.ept > 64) return set_error(SKEL_EINVAL, "ept out of range");
+        c.tile_h = 0;
+    } else if (L.dom == DOM_GRAY) {
+        // one 16-byte vector per lane in 512-lane groups measured fastest on
+        // volumes of 1 to 60 MiB
+        c.wg = o->wg ? o->wg : 512;
+        if (c.wg < 64 || c.wg > 1024 || c.wg % 64) return set_error(SKEL_EINVAL, "wg must be a multiple of 64 up to 1024");
+        c.ept = o->ept ? o->ept : 1;
         if (c.ept < 1 || c.ept > 64) return set_error(SKEL_EINVAL, "ept out of range");
         c.tile_h = 0;
     } else if (L.dom == DOM_C32) {
@@ -471,6 +498,42 @@ skel_status build_kernels(const Linear& L, const Shape& sh, const Config& c, std
             g.first = 1;
             g.name = "nbody_kick_drift";
             ks.push_back(g);
+        }
+        return SKEL_OK;
+    }
+    if (L.dom == DOM_GRAY) {
+        // One kernel per fused run of stages (all of them unless unfused or
+        // split by the mask).
+        const int k = (int)L.st.size();
+        int first = 0;
+        for (int i = 0; i < k; ++i) {
+            const bool split = i == k - 1 || c.fusion == SKEL_FUSE_OFF ||
+                               (c.fusion == SKEL_FUSE_MASK && ((c.split_mask >> i) & 1u)) || i - first + 1 == kMaxOps;
+            if (!split) continue;
+            Kernel K;
+            K.first = first;
+            K.last = i + 1;
+            K.wg = c.wg;
+            memset(&K.gray, 0, sizeof(K.gray));
+            K.gray.n = sh.n;
+            K.gray.ept = c.ept;
+            for (int j = first; j <= i; ++j) {
+                uint32_t lo = L.st[j].prm.lo, hi = L.st[j].prm.hi;
+                if (lo == 0 && hi == 0) lo = 85, hi = 170;
+                K.gray.lo[K.gray.nops] = (uint16_t)lo;
+                K.gray.hi[K.gray.nops] = (uint16_t)hi;
+                K.gray.nops++;
+            }
+            const int64_t nvec = (sh.n + 15) / 16;
+            K.grid = (int)((nvec + (int64_t)c.wg * c.ept - 1) / ((int64_t)c.wg * c.ept));
+            K.name = "gray_segment";
+            ks.push_back(K);
+            first = i + 1;
+        }
+        const int nk = (int)ks.size();
+        for (int g = 0; g < nk; ++g) {
+            ks[g].src = g == 0 ? -1 : ((g - 1) % 2);
+            ks[g].dst = g == nk - 1 ? -2 : (g % 2);
         }
         return SKEL_OK;
     }

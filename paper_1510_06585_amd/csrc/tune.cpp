@@ -52,7 +52,15 @@ std::vector<Config> enumerate_configs(const Linear& L, const Shape& sh) {
     else
         masks.push_back(0);
     for (uint32_t m : masks) {
-        if (L.dom == DOM_C32) {
+        if (L.dom == DOM_GRAY) {
+            for (int ept : {1, 8}) {
+                Config c = base;
+                c.fusion = k >= 1 ? SKEL_FUSE_MASK : SKEL_FUSE_ON;
+                c.split_mask = m;
+                c.ept = ept;
+                if (config_valid(L, sh, c)) out.push_back(c);
+            }
+        } else if (L.dom == DOM_C32) {
             Config c = base;
             c.fusion = k >= 1 ? SKEL_FUSE_MASK : SKEL_FUSE_ON;
             c.split_mask = m;
@@ -70,7 +78,7 @@ std::vector<Config> enumerate_configs(const Linear& L, const Shape& sh) {
             }
         } else {
             for (int wg : {64, 256, 1024})
-                for (int ept : {1, 4}) {
+                for (int ept : {1, 8}) {
                     Config c = base;
                     c.fusion = k >= 1 ? SKEL_FUSE_MASK : SKEL_FUSE_ON;
                     c.split_mask = m;
@@ -104,6 +112,7 @@ void features(const Linear& L, const Shape& sh, const Config& c, float* f) {
     const double n = L.dom == DOM_U8    ? (double)sh.W * sh.H
                      : L.dom == DOM_F32 ? (double)sh.n
                      : L.dom == DOM_C32 ? (double)sh.n * kFftPoints
+                     : L.dom == DOM_GRAY ? (double)sh.n
                                         : (double)sh.N;
     f[7] = (float)lg2(n);
     f[8] = L.dom == DOM_U8 ? 1.0f : 0.0f;
@@ -132,6 +141,7 @@ void features(const Linear& L, const Shape& sh, const Config& c, float* f) {
         if (L.dom == DOM_F32) bytes += ((K.dst == -3 ? 1.0 : 2.0) + K.side_args.size()) * n * 4.0;
         if (L.dom == DOM_NBODY) bytes += 48.0 * n;
         if (L.dom == DOM_C32) bytes += 16.0 * n;
+        if (L.dom == DOM_GRAY) bytes += 2.0 * n;
     }
     f[20] = (float)worst;
     f[21] = red_fused ? 1.0f : 0.0f;
@@ -357,10 +367,10 @@ int occupancy_of(const Linear& L, const Shape& sh, const Config& c) {
             worst = std::min(worst, img_waves_per_cu(K.img, K.blur, K.reduce, K.wg, c.variant));
         return worst;
     }
-    return 1;   // fp32 chains and N-body: no LDS, occupancy does not depend on wg here
+    return 1;   // fp32, gray and FFT chains, N-body: occupancy does not depend on wg here
 }
 
-int inner_value(const Linear& L, const Config& c) { return L.dom == DOM_F32 ? c.ept : c.tile_h; }
+int inner_value(const Linear& L, const Config& c) { return (L.dom == DOM_F32 || L.dom == DOM_GRAY) ? c.ept : c.tile_h; }
 
 }  // namespace
 

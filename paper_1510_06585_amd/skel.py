@@ -18,7 +18,7 @@ LIB_PATH = os.path.join(_HERE, "libskel.so")
 # --------------------------------------------------------------- constants
 OK, EINVAL, ESHAPE, ETYPE, ENOMEM, EDEVICE, EUNSUPPORTED = range(7)
 U8, U32, U64, F32, F64 = range(5)
-OP_NOISE, OP_SOLARISE, OP_MIRROR, OP_BLUR5, OP_SAXPY, OP_NBODY_FORCE, OP_LEAPFROG, OP_FFT, OP_IFFT = range(9)
+OP_NOISE, OP_SOLARISE, OP_MIRROR, OP_BLUR5, OP_SAXPY, OP_NBODY_FORCE, OP_LEAPFROG, OP_FFT, OP_IFFT, OP_SEGMENT = range(10)
 FFT_POINTS = 65536
 RED_HIST256_SUM, RED_SUM = 0, 1
 FUSE_AUTO, FUSE_OFF, FUSE_ON, FUSE_MASK = -1, 0, 1, 2
@@ -28,7 +28,7 @@ CMP_BY_NAME = {">": CMP_GT, ">=": CMP_GE, "<": CMP_LT, "<=": CMP_LE}
 
 OP_BY_NAME = {"noise": OP_NOISE, "solarise": OP_SOLARISE, "mirror": OP_MIRROR, "blur5": OP_BLUR5,
               "saxpy": OP_SAXPY, "nbody_force": OP_NBODY_FORCE, "leapfrog": OP_LEAPFROG, "fft": OP_FFT,
-              "ifft": OP_IFFT}
+              "ifft": OP_IFFT, "segment": OP_SEGMENT}
 STATUS_NAMES = {OK: "SKEL_OK", EINVAL: "SKEL_EINVAL", ESHAPE: "SKEL_ESHAPE", ETYPE: "SKEL_ETYPE",
                 ENOMEM: "SKEL_ENOMEM", EDEVICE: "SKEL_EDEVICE", EUNSUPPORTED: "SKEL_EUNSUPPORTED"}
 
@@ -47,7 +47,7 @@ class Buffer(ctypes.Structure):
 
 class Params(ctypes.Structure):
     _fields_ = [("seed", ctypes.c_uint32), ("a", ctypes.c_float), ("eps", ctypes.c_float),
-                ("G", ctypes.c_float), ("dt", ctypes.c_float)]
+                ("G", ctypes.c_float), ("dt", ctypes.c_float), ("lo", ctypes.c_uint32), ("hi", ctypes.c_uint32)]
 
 
 class LoopState(ctypes.Structure):
@@ -228,10 +228,11 @@ class Node:
             _lib.skel_node_release(h)
 
 
-def Map(op, seed: int = 0, a: float = 0.0, eps: float = 0.0, G: float = 0.0, dt: float = 0.0) -> Node:
+def Map(op, seed: int = 0, a: float = 0.0, eps: float = 0.0, G: float = 0.0, dt: float = 0.0, lo: int = 0,
+        hi: int = 0) -> Node:
     if isinstance(op, str):
         op = OP_BY_NAME[op]
-    p = Params(seed & 0xFFFFFFFF, a, eps, G, dt)
+    p = Params(seed & 0xFFFFFFFF, a, eps, G, dt, lo, hi)
     h = _node_p()
     _check(lib().skel_map(op, ctypes.byref(p), ctypes.byref(h)))
     return Node(h.value)
@@ -429,7 +430,8 @@ def image_chain(stages, reduce=None) -> Node:
     nodes = []
     for name, prm in stages:
         prm = prm or {}
-        nodes.append(Map(OP_BY_NAME[name], seed=prm.get("seed", 0), a=prm.get("a", 0.0)))
+        nodes.append(Map(OP_BY_NAME[name], seed=prm.get("seed", 0), a=prm.get("a", 0.0), lo=prm.get("lo", 0),
+                         hi=prm.get("hi", 0)))
     root = Pipeline(*nodes) if len(nodes) != 1 else nodes[0]
     if reduce is not None:
         root = MapReduce(root, RED_HIST256_SUM if reduce == "hist_sum" else RED_SUM)

@@ -19,6 +19,7 @@ SEED_NBODY = 3             # 65536-body Loop
 SEED_BATCH = 4             # 256 uneven batched requests
 SEED_SELECT = 5            # learned config selector compositions
 SEED_FFT = 6               # batched 65536-point FFT pipeline
+SEED_SEGMENT = 7           # gray volumes for Segmentation
 NOISE_SEED = 0x1510
 
 
@@ -46,6 +47,11 @@ def complex_batch(seed: int, B: int, N: int = 65536) -> np.ndarray:
     """B complex fp32 signals of N points as float32 [B, N, 2] (re, im), every
     component uniform in [-1, 1)."""
     return np.random.default_rng(seed).uniform(-1.0, 1.0, (B, N, 2)).astype(np.float32)
+
+
+def gray_volume(seed: int, D: int, H: int, W: int) -> np.ndarray:
+    """A gray uint8 volume [D, H, W], every voxel uniform in 0..255."""
+    return np.random.default_rng(seed).integers(0, 256, (D, H, W), dtype=np.uint8)
 
 
 def nbody(seed: int, N: int):
