@@ -620,8 +620,10 @@ skel_status skel_plan_describe(skel_plan p, char* buf, size_t len) {
                  k.grid, k.wg, p->lin.dom == DOM_U8 ? k.img.tile_h : p->cfg.tile_h);
         s += tmp;
     }
-    snprintf(tmp, sizeof(tmp), "],\"config\":{\"fusion\":%d,\"split_mask\":%u,\"tile_h\":%d,\"wg\":%d,\"ept\":%d,\"variant\":%d}}",
-             p->cfg.fusion, p->cfg.split_mask, p->cfg.tile_h, p->cfg.wg, p->cfg.ept, p->cfg.variant);
+    snprintf(tmp, sizeof(tmp),
+             "],\"batch_grid\":%d,\"config\":{\"fusion\":%d,\"split_mask\":%u,\"tile_h\":%d,\"wg\":%d,\"ept\":%d,"
+             "\"variant\":%d}}",
+             p->batch_grid, p->cfg.fusion, p->cfg.split_mask, p->cfg.tile_h, p->cfg.wg, p->cfg.ept, p->cfg.variant);
     s += tmp;
     strncpy(buf, s.c_str(), len - 1);
     buf[len - 1] = 0;

@@ -494,22 +494,46 @@ __global__ void __launch_bounds__(256) img_band_kernel(const ImgGroupArgs A) {
     }
 }
 
-// Persistent batched kernel: every wavefront takes tiles from a global ticket
-// counter until the work list is exhausted, looks up the owning request in the
+// A request descriptor read into scalar registers word by word: every lane
+// loads the same address, and without the read-back the pointers and sizes
+// would stay in vector registers, turning all of the tile's addressing into
+// per-lane arithmetic.
+static __device__ __forceinline__ BatchReq uniform_req(const BatchReq* p) {
+    static_assert(sizeof(BatchReq) % 4 == 0, "descriptor is whole words");
+    BatchReq r;
+    const uint32_t* src = reinterpret_cast<const uint32_t*>(p);
+    uint32_t* dst = reinterpret_cast<uint32_t*>(&r);
+#pragma unroll
+    for (int i = 0; i < (int)(sizeof(BatchReq) / 4); ++i) dst[i] = (uint32_t)wave_uniform((int)src[i]);
+    return r;
+}
+
+// Persistent batched kernel: every work-group takes a group of consecutive
+// tiles (one per wavefront: adjacent bands of the same rows, so the group
+// streams contiguous row segments through one CU's cache, as a work-group of
+// the single-image kernel does) from a global ticket counter until the work
+// list is exhausted.  Each wavefront looks up its tile's request in the
 // tile -> request table, runs the fused chain on the tile and stores its own
 // LDS histogram as the tile's histogram row.
 template <int PRE, int POST, bool BLUR, bool HIST, int FL>
 __global__ void __launch_bounds__(256) img_batch_kernel(const BatchArgs A) {
     __shared__ uint32_t lh_all[HIST ? 4 * 4 * kHistWaveChan : 1];
+    __shared__ uint32_t ticket[2];
     const int lane = threadIdx.x & 63;
     const int wave = wave_uniform(threadIdx.x >> 6);
+    const uint32_t nw = blockDim.x >> 6;
     uint32_t* lh = HIST ? lh_all + wave * 4 * kHistWaveChan : lh_all;
-    for (;;) {
-        uint32_t t = 0;
-        if (lane == 0) t = atomicAdd(A.counter, 1u);
-        t = (uint32_t)wave_uniform((int)t);
-        if (t >= (uint32_t)A.ntiles) break;
-        const BatchReq R = A.reqs[A.tile_req[t]];
+    // ticket[] alternates between iterations: thread 0 writes slot i & 1 only
+    // after the barrier of iteration i, which every wavefront reaches after
+    // reading the same slot in iteration i - 2.
+    for (uint32_t it = 0;; ++it) {
+        if (threadIdx.x == 0) ticket[it & 1] = atomicAdd(A.counter, 1u);
+        __syncthreads();
+        const uint32_t first = (uint32_t)wave_uniform((int)ticket[it & 1]) * nw;
+        if (first >= (uint32_t)A.ntiles) break;   // uniform over the work-group
+        const uint32_t t = first + (uint32_t)wave;
+        if (t >= (uint32_t)A.ntiles) continue;
+        const BatchReq R = uniform_req(A.reqs + wave_uniform((int)A.tile_req[t]));
         const int lt = (int)t - R.tile_begin;
         const int band = lt % R.nbands;
         const int chunk = lt / R.nbands;

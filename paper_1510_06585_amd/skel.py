@@ -193,6 +193,22 @@ def bind(bufs) -> Bound:
     return Bound(bufs)
 
 
+class BoundBatch:
+    """Pre-marshalled request list for Plan.batch_run (one argument list per
+    request, flattened request by request)."""
+
+    def __init__(self, reqs):
+        reqs = list(reqs)
+        self.per = len(reqs[0]) if reqs else 0
+        self.nreq = len(reqs)
+        self.tensors = [a for r in reqs for a in r]
+        self.arr, _ = _buf_array(self.tensors)
+
+
+def bind_batch(reqs) -> BoundBatch:
+    return BoundBatch(reqs)
+
+
 def _buf_array(bufs):
     if isinstance(bufs, Bound):
         return bufs.arr, bufs.n
@@ -311,10 +327,10 @@ class Plan:
         _check(lib().skel_plan_run_event(self._h, arr, n, _stream_handle(stream), ev))
 
     def batch_run(self, reqs, stream=None):
-        flat = [a for r in reqs for a in r]
-        per = len(reqs[0]) if reqs else 0
-        arr, _ = _buf_array(flat)
-        _check(lib().skel_batch_run(self._h, arr, per, len(reqs), _stream_handle(stream)))
+        """reqs: a list of per-request argument lists, or a BoundBatch."""
+        if not isinstance(reqs, BoundBatch):
+            reqs = BoundBatch(reqs)
+        _check(lib().skel_batch_run(self._h, reqs.arr, reqs.per, reqs.nreq, _stream_handle(stream)))
 
     def describe(self) -> dict:
         buf = ctypes.create_string_buffer(1 << 16)

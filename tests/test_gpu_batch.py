@@ -40,10 +40,14 @@ def test_small_uneven_batch_against_oracle():
     rng = np.random.default_rng(21)
     sides = [(int(rng.integers(1, 300)), int(rng.integers(1, 700))) for _ in range(40)] + [(0, 5), (3, 0)]
     reqs, imgs = make_reqs(sides, 1000)
-    for opt in ({"tile_h": 16}, {"tile_h": 5, "wg": 64}):
+    bound = sk.bind_batch(reqs)
+    # one, two and four wavefronts per work-group take groups of consecutive tiles
+    for opt in ({"tile_h": 16}, {"tile_h": 5, "wg": 64}, {"tile_h": 7, "wg": 128}):
         p = plan_for(CFG2, options=opt)
-        for rep in range(2):   # capture, then replay of the same request set
-            p.batch_run(reqs)
+        for rep in range(2):   # capture, then replay of the same request set (pre-marshalled)
+            for a in reqs:
+                a[1].fill_(7)
+            p.batch_run(reqs if rep == 0 else bound)
             torch.cuda.synchronize()
             for (H, W), img, a in zip(sides, imgs, reqs):
                 ref, rh, rs = oracle.run_image_pipeline(img, CFG2, "hist_sum")
