@@ -4,8 +4,9 @@
 // (longest-processing-time order, so the tail of the launch is made of small
 // tiles), and captures [reset ticket, clear outputs, persistent kernel,
 // histogram merge] into a HIP graph that is replayed while the same buffers
-// and shapes come back.  Every tile stores its histogram as a row; the merge
-// sums each request's rows in chunks and adds them to its outputs.
+// and shapes come back.  Every group of tiles (one per wavefront of a
+// work-group, all of one request) stores its work-group histogram as a row;
+// the merge sums each request's rows in chunks and adds them to its outputs.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -134,6 +135,10 @@ extern "C" skel_status skel_batch_run(skel_plan p, const skel_buffer* args, int3
         p->d_reqs_cap = nreq;
     }
     if (!p->d_counter) HIP_TRY(hipMalloc(&p->d_counter, 256));
+    // Tiles are handed out in groups of one per wavefront of a work-group;
+    // every request's tile range is padded to whole groups, so a group (and
+    // its histogram row) belongs to one request.
+    const int gw = K.wg / 64;
     int64_t tiles = 0, chunks = 0;
     for (int k = 0; k < nreq; ++k) {
         const skel_buffer* a = args + (size_t)order[k] * nargs;
@@ -150,25 +155,27 @@ extern "C" skel_status skel_batch_run(skel_plan p, const skel_buffer* args, int3
         R.nchunks = (R.H + R.tile_h - 1) / R.tile_h;
         R.tile_begin = (int32_t)tiles;
         const int64_t nt = (R.W > 0 && R.H > 0) ? (int64_t)R.nbands * R.nchunks : 0;
-        tiles += nt;
+        const int64_t ngroups = (nt + gw - 1) / gw;
+        tiles += ngroups * gw;
         if (tiles >= ((int64_t)1 << 31)) return set_error(SKEL_EUNSUPPORTED, "batch has too many tiles");
         HistSeg& G = p->h_segs[k];
         memset(&G, 0, sizeof(G));
         G.hist = R.hist;
         G.sum = R.sum;
-        G.row_begin = R.tile_begin;
-        G.nrows = (int32_t)nt;
+        G.row_begin = R.tile_begin / gw;
+        G.nrows = (int32_t)ngroups;
         G.crows = hist_chunk_rows(K.bins);
         G.chunk_begin = (int32_t)chunks;
-        chunks += hist_chunks((int)nt, G.crows);
+        chunks += hist_chunks((int)ngroups, G.crows);
     }
     const size_t words = 4 * (size_t)K.bins;
-    if (red >= 0 && (size_t)tiles * words > p->b_rows_cap) {
+    const size_t rows = (size_t)(tiles / gw);
+    if (red >= 0 && rows * words > p->b_rows_cap) {
         if (p->b_rows) hipFree(p->b_rows);
         p->b_rows = nullptr;
         p->b_rows_cap = 0;
-        HIP_TRY(hipMalloc(&p->b_rows, sizeof(uint32_t) * tiles * words));
-        p->b_rows_cap = (size_t)tiles * words;
+        HIP_TRY(hipMalloc(&p->b_rows, sizeof(uint32_t) * rows * words));
+        p->b_rows_cap = rows * words;
     }
     // Tile -> request table (tiles are numbered request by request).
     std::vector<uint16_t> tile_req((size_t)tiles);
@@ -198,7 +205,7 @@ extern "C" skel_status skel_batch_run(skel_plan p, const skel_buffer* args, int3
     A.in_flip = K.img.in_flip;
     A.out_flip = K.img.out_flip;
     A.has_hist = red >= 0;
-    A.hist_ks = hist_copies_log2(K.bins, kHistWaveWords);
+    A.hist_ks = hist_copies_log2(K.bins, kHistWgWords);
     A.bins = K.bins;
     A.part = p->b_rows;
     A.counter = p->d_counter;
@@ -210,7 +217,7 @@ extern "C" skel_status skel_batch_run(skel_plan p, const skel_buffer* args, int3
     int per_cu = img_batch_blocks_per_cu(A, wg);
     if (per_cu < 1) per_cu = 1;
     int grid = per_cu * prop.multiProcessorCount;
-    const int need = (int)((tiles + wg / 64 - 1) / (wg / 64));
+    const int need = (int)(tiles / gw);
     grid = std::max(1, std::min(grid, need));
     p->batch_grid = grid;
 

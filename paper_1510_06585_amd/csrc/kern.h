@@ -51,7 +51,6 @@ struct ImgGroupArgs {
 // region of `words` counters.
 int hist_copies_log2(int bins, int words);
 constexpr int kHistWgWords = 2048;     // per channel, one histogram per work-group
-constexpr int kHistWaveWords = 512;    // per channel, one histogram per wavefront
 
 // Compile-time encoding of a value-stage run for specialised kernels:
 // sum of op_k * 4^k; -1 selects the generic stage interpreter.
@@ -123,7 +122,7 @@ struct BatchReq {
     uint64_t* sum;
     int32_t W, H;
     int32_t nbands, nchunks;
-    int32_t tile_begin;  // first global tile index of this request
+    int32_t tile_begin;  // first global tile index of this request (a multiple of the wavefronts per group)
     int32_t tile_h;      // rows per tile of this request
 };
 struct BatchArgs {
@@ -134,10 +133,10 @@ struct BatchArgs {
     int32_t has_blur;
     int32_t in_flip, out_flip;
     int32_t has_hist;
-    int32_t hist_ks;     // log2 copies per bin of the per-wavefront histograms
+    int32_t hist_ks;     // log2 copies per bin of the work-group histograms
     int32_t bins;        // values emitted are < bins
     int32_t pad;
-    uint32_t* part;      // histogram rows, one per tile (global tile index)
+    uint32_t* part;      // histogram rows, one per tile group (ticket)
     uint32_t* counter;   // work-queue ticket counter (zeroed before launch)
     OpList pre, post;
 };

@@ -177,12 +177,10 @@ static __device__ __forceinline__ int clampi(int v, int lo, int hi) { return v <
 constexpr int kPrefetch = 4;
 static_assert(kPrefetch == 4, "row groups are written out for four slots (the blur ring length)");
 
-// Histogram modes: none, one privatised histogram per work-group, one per
-// wavefront (persistent batched kernel).  Per channel a work-group histogram
-// has kHistWgChan counter words = bins x copies, a wavefront one kHistWaveChan.
-enum { HIST_NONE = 0, HIST_WG = 1, HIST_WAVE = 2 };
+// Histogram modes: none, or one privatised histogram per work-group with
+// kHistWgChan counter words = bins x copies per channel.
+enum { HIST_NONE = 0, HIST_WG = 1 };
 constexpr int kHistWgChan = 2048;
-constexpr int kHistWaveChan = 512;
 
 // Per-tile geometry and addressing of one image.
 struct ImgView {
@@ -223,7 +221,7 @@ static __device__ __forceinline__ void band_tile(const ImgView& V, const OpList&
     // Histogram addressing: counter (c, v, copy) lives at word
     // c * CS + v * 2^hks + copy, copy = lane mod 2^hks; a u16 pair {v0, v1}
     // shifted left by hks + 2 gives both byte offsets in its halves.
-    constexpr int CS = HM == HIST_WAVE ? kHistWaveChan : kHistWgChan;
+    constexpr int CS = kHistWgChan;
     const uint32_t hsh = (uint32_t)hks + 2u;
     const uint32_t lane_off = ((uint32_t)lane & ((1u << hks) - 1u)) * 4u;
     char* const lhb = reinterpret_cast<char*>(lh);
@@ -440,17 +438,21 @@ static __device__ __forceinline__ void band_tile(const ImgView& V, const OpList&
 // the histogram finalise kernels, so no device-wide atomics are needed.
 // Counter (c, v, copy) is at word c * CS + v * 2^hks + copy; thread order
 // starts each bin's copy sum at a different copy to spread LDS banks.
-template <int CS>
-static __device__ __forceinline__ void write_hist_row(const uint32_t* lh, int hks, uint32_t* row, int first,
-                                                      int step) {
+// With CLEAR every counter is zeroed after it is read (each word is read by
+// one thread only), leaving the histogram ready for the next tile group.
+template <int CS, bool CLEAR = false>
+static __device__ __forceinline__ void write_hist_row(uint32_t* lh, int hks, uint32_t* row, int first, int step) {
     const int copies = 1 << hks;
     const int bins = CS >> hks;
     for (int b = first; b < 4 * bins; b += step) {
         const int c = b >> (__builtin_ctz((unsigned)bins));
         const int v = b & (bins - 1);
-        const uint32_t* w = lh + c * CS + (v << hks);
+        uint32_t* w = lh + c * CS + (v << hks);
         uint32_t n = 0;
-        for (int j = 0; j < copies; ++j) n += w[(j + v) & (copies - 1)];
+        for (int j = 0; j < copies; ++j) {
+            n += w[(j + v) & (copies - 1)];
+            if (CLEAR) w[(j + v) & (copies - 1)] = 0;
+        }
         row[b] = n;
     }
 }
@@ -512,47 +514,46 @@ static __device__ __forceinline__ BatchReq uniform_req(const BatchReq* p) {
 // tiles (one per wavefront: adjacent bands of the same rows, so the group
 // streams contiguous row segments through one CU's cache, as a work-group of
 // the single-image kernel does) from a global ticket counter until the work
-// list is exhausted.  Each wavefront looks up its tile's request in the
-// tile -> request table, runs the fused chain on the tile and stores its own
-// LDS histogram as the tile's histogram row.
+// list is exhausted.  The host pads every request's tiles to whole groups, so
+// a group never spans two requests: its wavefronts count into one
+// work-group histogram, stored as the group's histogram row (row = ticket).
+// Each wavefront looks up its tile's request in the tile -> request table;
+// padding tiles (past the request's last tile) do nothing.
 template <int PRE, int POST, bool BLUR, bool HIST, int FL>
 __global__ void __launch_bounds__(256) img_batch_kernel(const BatchArgs A) {
-    __shared__ uint32_t lh_all[HIST ? 4 * 4 * kHistWaveChan : 1];
+    __shared__ uint32_t lh[HIST ? 4 * kHistWgChan : 1];
     __shared__ uint32_t ticket[2];
     const int lane = threadIdx.x & 63;
     const int wave = wave_uniform(threadIdx.x >> 6);
     const uint32_t nw = blockDim.x >> 6;
-    uint32_t* lh = HIST ? lh_all + wave * 4 * kHistWaveChan : lh_all;
+    if constexpr (HIST)
+        for (int b = threadIdx.x; b < 4 * kHistWgChan; b += blockDim.x) lh[b] = 0;
     // ticket[] alternates between iterations: thread 0 writes slot i & 1 only
-    // after the barrier of iteration i, which every wavefront reaches after
-    // reading the same slot in iteration i - 2.
+    // after the barrier of iteration i - 1, which every wavefront reaches
+    // after reading the same slot in iteration i - 2.  That barrier also
+    // orders the previous group's histogram read-and-clear before new counts.
     for (uint32_t it = 0;; ++it) {
         if (threadIdx.x == 0) ticket[it & 1] = atomicAdd(A.counter, 1u);
         __syncthreads();
-        const uint32_t first = (uint32_t)wave_uniform((int)ticket[it & 1]) * nw;
-        if (first >= (uint32_t)A.ntiles) break;   // uniform over the work-group
-        const uint32_t t = first + (uint32_t)wave;
-        if (t >= (uint32_t)A.ntiles) continue;
+        const uint32_t g = (uint32_t)wave_uniform((int)ticket[it & 1]);
+        if (g * nw >= (uint32_t)A.ntiles) break;   // uniform over the work-group
+        const uint32_t t = g * nw + (uint32_t)wave;
         const BatchReq R = uniform_req(A.reqs + wave_uniform((int)A.tile_req[t]));
         const int lt = (int)t - R.tile_begin;
-        const int band = lt % R.nbands;
-        const int chunk = lt / R.nbands;
-        const int y0 = chunk * R.tile_h;
-        const int y1 = min(y0 + R.tile_h, R.H);
-        if constexpr (HIST) {
-            for (int b = lane; b < 4 * kHistWaveChan; b += 64) lh[b] = 0;
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-            __builtin_amdgcn_wave_barrier();
+        if (lt < R.nbands * R.nchunks) {
+            const int band = lt % R.nbands;
+            const int chunk = lt / R.nbands;
+            const int y0 = chunk * R.tile_h;
+            const int y1 = min(y0 + R.tile_h, R.H);
+            const ImgView V{R.in, R.out, R.W, R.H, FL < 0 ? A.in_flip : (FL & 1), FL < 0 ? A.out_flip : (FL >> 1),
+                            1};
+            band_tile<PRE, POST, BLUR, HIST ? HIST_WG : HIST_NONE>(V, A.pre, A.post, band, y0, y1, lane, lh,
+                                                                    A.hist_ks);
         }
-        const ImgView V{R.in, R.out, R.W, R.H, FL < 0 ? A.in_flip : (FL & 1), FL < 0 ? A.out_flip : (FL >> 1), 1};
-        band_tile<PRE, POST, BLUR, HIST ? HIST_WAVE : HIST_NONE>(V, A.pre, A.post, band, y0, y1, lane, lh,
-                                                                  A.hist_ks);
         if constexpr (HIST) {
-            __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
-            __builtin_amdgcn_wave_barrier();
-            write_hist_row<kHistWaveChan>(lh, A.hist_ks, A.part + (size_t)t * 4 * A.bins, lane, 64);
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-            __builtin_amdgcn_wave_barrier();
+            __syncthreads();
+            write_hist_row<kHistWgChan, true>(lh, A.hist_ks, A.part + (size_t)g * 4 * A.bins, threadIdx.x,
+                                              blockDim.x);
         }
     }
 }
@@ -704,7 +705,7 @@ __global__ void fill_u32_kernel(uint32_t* p, uint64_t n, uint32_t v) {
 }
 
 // ------------------------------------------------------------------ host side
-static_assert(kHistWgChan == kHistWgWords && kHistWaveChan == kHistWaveWords, "histogram layout");
+static_assert(kHistWgChan == kHistWgWords, "histogram layout");
 
 int hist_copies_log2(int bins, int words) {
     int ks = 0;
