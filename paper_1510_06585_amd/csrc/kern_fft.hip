@@ -42,8 +42,12 @@ static __device__ __forceinline__ cpx csub(cpx a, cpx b) { return {a.x - b.x, a.
 static __device__ __forceinline__ cpx cmul(cpx a, cpx b) {
     return {__builtin_fmaf(a.x, b.x, -a.y * b.y), __builtin_fmaf(a.x, b.y, a.y * b.x)};
 }
-// a * (dir * i): dir = -1 forward, +1 inverse.
-static __device__ __forceinline__ cpx cmul_i(cpx a, int dir) { return dir < 0 ? cpx{a.y, -a.x} : cpx{-a.y, a.x}; }
+// The transform direction DIR is a template parameter: -1 forward
+// (W = exp(-2 pi i / N)), +1 inverse, so no twiddle carries a run-time sign.
+
+// a * (DIR * i)
+template <int DIR>
+static __device__ __forceinline__ cpx cmul_i(cpx a) { return DIR < 0 ? cpx{a.y, -a.x} : cpx{-a.y, a.x}; }
 
 // Roots of unity in LDS: TH[h] = W^(256 h) and TL[l] = W^l (h, l < 256,
 // W = exp(2 pi i / N)), so W^m = TH[m >> 8] TL[m & 255] from two reads
@@ -60,17 +64,34 @@ static __device__ __forceinline__ void load_tw(TwLds& L, const float2* T) {
     }
 }
 
-// W_N^m in direction dir: (cos, dir * sin)(2 pi m / N), m taken mod N.
-static __device__ __forceinline__ cpx tw(const TwLds& L, uint32_t m, int dir) {
+// W_N^m in direction DIR: (cos, DIR * sin)(2 pi m / N), m taken mod N.
+template <int DIR>
+static __device__ __forceinline__ cpx tw(const TwLds& L, uint32_t m) {
     m &= (uint32_t)(kFftN - 1);
     cpx w = L.hi[m >> 8];
     if (m & 255u) w = cmul(w, L.lo[m & 255u]);
-    return {w.x, dir < 0 ? -w.y : w.y};
+    return {w.x, DIR < 0 ? -w.y : w.y};
 }
 
-// In-register 4-point DFT of (a, b, c, d) in direction dir.
-static __device__ __forceinline__ void dft4(cpx& a, cpx& b, cpx& c, cpx& d, int dir) {
-    const cpx s0 = cadd(a, c), d0 = csub(a, c), s1 = cadd(b, d), d1 = cmul_i(csub(b, d), dir);
+// a * W_16^K in direction DIR, the root as a compile-time constant.
+template <int DIR, int K>
+static __device__ __forceinline__ cpx rot16(cpx a) {
+    constexpr float c8 = 0.92387953251128674f, s8 = 0.38268343236508978f, r2 = 0.70710678118654752f;
+    constexpr int k = K % 16;
+    if constexpr (k == 0) return a;
+    else if constexpr (k == 4) return cmul_i<DIR>(a);
+    else {
+        constexpr float cs[16][2] = {{1, 0},   {c8, s8},   {r2, r2},   {s8, c8},   {0, 1},   {-s8, c8},
+                                     {-r2, r2}, {-c8, s8}, {-1, 0},    {-c8, -s8}, {-r2, -r2}, {-s8, -c8},
+                                     {0, -1},  {s8, -c8},  {r2, -r2},  {c8, -s8}};
+        return cmul(a, cpx{cs[k][0], DIR < 0 ? -cs[k][1] : cs[k][1]});
+    }
+}
+
+// In-register 4-point DFT of (a, b, c, d).
+template <int DIR>
+static __device__ __forceinline__ void dft4(cpx& a, cpx& b, cpx& c, cpx& d) {
+    const cpx s0 = cadd(a, c), d0 = csub(a, c), s1 = cadd(b, d), d1 = cmul_i<DIR>(csub(b, d));
     a = cadd(s0, s1);
     c = csub(s0, s1);
     b = cadd(d0, d1);
@@ -80,19 +101,27 @@ static __device__ __forceinline__ void dft4(cpx& a, cpx& b, cpx& c, cpx& d, int 
 // In-register 16-point DFT, v[c] -> v[k] in natural order, as 4 x 4:
 // c = c1 + 4 c2, k = k2 + 4 k1; a 4-point DFT over c2, the twiddle
 // W_16^(c1 k2), a 4-point DFT over c1.
-static __device__ __forceinline__ void dft16(cpx (&v)[16], const TwLds& T, int dir) {
+template <int DIR, int C1 = 1>
+static __device__ __forceinline__ void twiddle16(cpx (&v)[16]) {
+    if constexpr (C1 < 4) {
+        v[C1 + 4] = rot16<DIR, C1 * 1>(v[C1 + 4]);
+        v[C1 + 8] = rot16<DIR, C1 * 2>(v[C1 + 8]);
+        v[C1 + 12] = rot16<DIR, C1 * 3>(v[C1 + 12]);
+        twiddle16<DIR, C1 + 1>(v);
+    }
+}
+
+template <int DIR>
+static __device__ __forceinline__ void dft16(cpx (&v)[16]) {
 #pragma unroll
-    for (int c1 = 0; c1 < 4; ++c1) dft4(v[c1], v[c1 + 4], v[c1 + 8], v[c1 + 12], dir);
+    for (int c1 = 0; c1 < 4; ++c1) dft4<DIR>(v[c1], v[c1 + 4], v[c1 + 8], v[c1 + 12]);
     // v[c1 + 4 k2] now holds U[c1][k2]
-#pragma unroll
-    for (int c1 = 1; c1 < 4; ++c1)
-#pragma unroll
-        for (int k2 = 1; k2 < 4; ++k2) v[c1 + 4 * k2] = cmul(v[c1 + 4 * k2], tw(T, (uint32_t)(c1 * k2) * (kFftN / 16), dir));
+    twiddle16<DIR>(v);
     cpx o[16];
 #pragma unroll
     for (int k2 = 0; k2 < 4; ++k2) {
         cpx a = v[0 + 4 * k2], b = v[1 + 4 * k2], c = v[2 + 4 * k2], d = v[3 + 4 * k2];
-        dft4(a, b, c, d, dir);
+        dft4<DIR>(a, b, c, d);
         o[k2] = a;
         o[k2 + 4] = b;
         o[k2 + 8] = c;
@@ -102,18 +131,20 @@ static __device__ __forceinline__ void dft16(cpx (&v)[16], const TwLds& T, int d
     for (int k = 0; k < 16; ++k) v[k] = o[k];
 }
 
-// 256-point DFTs of the kFftCols rows of S (S[j][m], m = 0..255) in direction
-// dir, in place, natural order; thread t works on row t / 16.  Ends
-// synchronised.
-static __device__ __forceinline__ void dft256_rows(cpx* S, const TwLds& T, int dir) {
+// 256-point DFTs of the kFftCols rows of a tile, thread t working on row
+// j = t / 16 with u = t % 16: on entry v[c] = x[u + 16 c] of row j, on exit
+// v[q] = X[u + 16 q].  The input and output element sets of a thread are the
+// same, so a second transform of the same rows (the fused pass) starts from
+// the registers.  S is the LDS tile used for the transposition in between;
+// the call starts with a barrier (other threads may still read S) and ends
+// without one.
+template <int DIR>
+static __device__ __forceinline__ void dft256_reg(cpx* S, const TwLds& T, cpx (&v)[16]) {
     const int j = threadIdx.x >> 4, u = threadIdx.x & 15;
-    cpx v[16];
     // m = a + 16 c with a = u: 16-point DFT over c, twiddle W_256^(a p).
+    dft16<DIR>(v);
 #pragma unroll
-    for (int c = 0; c < 16; ++c) v[c] = S[sx(j, u + 16 * c)];
-    dft16(v, T, dir);
-#pragma unroll
-    for (int p = 1; p < 16; ++p) v[p] = cmul(v[p], tw(T, (uint32_t)(u * p) * (kFftN / kFftR), dir));
+    for (int p = 1; p < 16; ++p) v[p] = cmul(v[p], tw<DIR>(T, (uint32_t)(u * p) * (kFftN / kFftR)));
     __syncthreads();
 #pragma unroll
     for (int p = 0; p < 16; ++p) S[sx(j, 16 * p + u)] = v[p];   // Z[a = u][p] at 16 p + a
@@ -121,11 +152,26 @@ static __device__ __forceinline__ void dft256_rows(cpx* S, const TwLds& T, int d
     // for p = u: 16-point DFT over a -> k = p + 16 q
 #pragma unroll
     for (int a = 0; a < 16; ++a) v[a] = S[sx(j, 16 * u + a)];
-    dft16(v, T, dir);
-    __syncthreads();
+    dft16<DIR>(v);
+}
+
+static __device__ __forceinline__ void dft256_reg(cpx* S, const TwLds& T, cpx (&v)[16], int dir) {
+    if (dir < 0)
+        dft256_reg<-1>(S, T, v);
+    else
+        dft256_reg<1>(S, T, v);
+}
+
+// Twiddle W_N^(n1 k2) (n1 = kFftCols g + j, k2 = m) and store T[k2][n1].
+template <int DIR>
+static __device__ __forceinline__ void store_twiddled(const cpx* S, const TwLds& W, cpx* out, int g) {
+    const int t = threadIdx.x;
 #pragma unroll
-    for (int q = 0; q < 16; ++q) S[sx(j, u + 16 * q)] = v[q];
-    __syncthreads();
+    for (int i = 0; i < 16; ++i) {
+        const int e = t + kFftThreads * i, j = e % kFftCols, m = e / kFftCols;
+        const cpx w = tw<DIR>(W, (uint32_t)(kFftCols * g + j) * (uint32_t)m);
+        out[m * kFftR + kFftCols * g + j] = cmul(S[sx(j, m)], w);
+    }
 }
 
 // MODE 0 (A): in natural order -> T layout; MODE 1 (BA): T -> T (pass B of
@@ -142,41 +188,49 @@ __global__ void __launch_bounds__(kFftThreads) fft_pass_kernel(const FftArgs A) 
     const int t = threadIdx.x;
     const cpx* in = reinterpret_cast<const cpx*>(A.in) + (size_t)b * kFftN;
     cpx* out = reinterpret_cast<cpx*>(A.out) + (size_t)b * kFftN;
-    // load: element (j, m) of the tile into S[j][m]
+    const int j = t >> 4, u = t & 15;
+    cpx v[16];   // v[c] = element u + 16 c of row j of the tile
     if (MODE == 0) {
-        // column n1 = kFftCols g + j, rows n2 = m: x[n1 + 256 m]
+        // column n1 = kFftCols g + j, rows n2 = m: x[n1 + 256 m], staged
+        // through LDS (a thread's own elements are 32-byte pieces of 16 rows)
 #pragma unroll
         for (int i = 0; i < 16; ++i) {
-            const int e = t + kFftThreads * i, j = e % kFftCols, m = e / kFftCols;
-            S[sx(j, m)] = in[kFftCols * g + j + kFftR * m];
+            const int e = t + kFftThreads * i, jj = e % kFftCols, m = e / kFftCols;
+            S[sx(jj, m)] = in[kFftCols * g + jj + kFftR * m];
         }
+        __syncthreads();
+#pragma unroll
+        for (int c = 0; c < 16; ++c) v[c] = S[sx(j, u + 16 * c)];
     } else {
-        // row k2 = kFftCols g + j of T: T[k2][m] at k2 * 256 + m
+        // row k2 = kFftCols g + j of T (T[k2][m] at k2 * 256 + m), straight
+        // into registers: for each c the 16 threads of a row read one
+        // 128-byte run
+        const cpx* row = in + (size_t)(kFftCols * g + j) * kFftR;
 #pragma unroll
-        for (int i = 0; i < 16; ++i) {
-            const int e = t + kFftThreads * i, j = e / kFftR, m = e % kFftR;
-            S[sx(j, m)] = in[(kFftCols * g + j) * kFftR + m];
+        for (int c = 0; c < 16; ++c) v[c] = row[u + 16 * c];
+        __syncthreads();   // the twiddle tables
+    }
+    {
+        dft256_reg(S, W, v, A.dir1);
+        if (MODE == 1) {
+            // v[q] = X[k2 + 256 k1] of the first stage at k1 = u + 16 q (k2 =
+            // kFftCols g + j): the second stage's input at n1' = k2, n2' = k1,
+            // i.e. exactly what its transform of row j starts from.
+            if (A.scale1 != 1.0f)
+#pragma unroll
+                for (int q = 0; q < 16; ++q) v[q] = {v[q].x * A.scale1, v[q].y * A.scale1};
+            dft256_reg(S, W, v, A.dir2);
         }
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < 16; ++q) S[sx(j, u + 16 * q)] = v[q];
     }
     __syncthreads();
-    dft256_rows(S, W, A.dir1);
-    if (MODE == 1) {
-        // S[j][k1] = X[k2 + 256 k1] of the first stage (k2 = kFftCols g + j): it
-        // is the second stage's input at n1' = k2, n2' = k1.
-        if (A.scale1 != 1.0f)
-            for (int e = t; e < kFftCols * kRowStride; e += kFftThreads) S[e] = {S[e].x * A.scale1, S[e].y * A.scale1};
-        __syncthreads();
-        dft256_rows(S, W, A.dir2);
-    }
     if (MODE == 0 || MODE == 1) {
-        // twiddle W_N^(n1 k2) (n1 = kFftCols g + j, k2 = m) and store T[k2][n1]
-        const int dir = MODE == 0 ? A.dir1 : A.dir2;
-#pragma unroll
-        for (int i = 0; i < 16; ++i) {
-            const int e = t + kFftThreads * i, j = e % kFftCols, m = e / kFftCols;
-            const cpx w = tw(W, (uint32_t)(kFftCols * g + j) * (uint32_t)m, dir);
-            out[m * kFftR + kFftCols * g + j] = cmul(S[sx(j, m)], w);
-        }
+        if ((MODE == 0 ? A.dir1 : A.dir2) < 0)
+            store_twiddled<-1>(S, W, out, g);
+        else
+            store_twiddled<1>(S, W, out, g);
     } else {
         // X[k2 + 256 k1] with k2 = kFftCols g + j, k1 = m
 #pragma unroll
