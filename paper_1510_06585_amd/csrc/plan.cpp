@@ -262,11 +262,15 @@ skel_status derive_shape(const Linear& L, const skel_buffer* proto, int32_t narg
     }
     if (L.dom == DOM_GRAY) {
         if (proto[0].ndim < 1 || proto[0].ndim > 4) return set_error(SKEL_ESHAPE, "argument 0: 1..4 dims");
-        int64_t n = 1;
-        for (int d = 0; d < proto[0].ndim; ++d) n *= proto[0].shape[d];
         if ((st = check_buf(proto[0], 0, SKEL_U8, proto[0].ndim, proto[0].shape))) return st;
         if ((st = check_buf(proto[1], 1, SKEL_U8, proto[0].ndim, proto[0].shape))) return st;
-        if (n >= ((int64_t)1 << 31)) return set_error(SKEL_EUNSUPPORTED, "volumes are limited to 2 GiB");
+        int64_t n = 1;
+        for (int d = 0; d < proto[0].ndim && n > 0; ++d) {
+            if (proto[0].shape[d] >= ((int64_t)1 << 31)) return set_error(SKEL_EUNSUPPORTED, "volumes are limited to 2 GiB");
+            n *= proto[0].shape[d];   // < 2^62: no overflow
+            if (n >= ((int64_t)1 << 31)) return set_error(SKEL_EUNSUPPORTED, "volumes are limited to 2 GiB");
+        }
+        if (n < 0) n = 0;
         sh.n = n;
         return SKEL_OK;
     }

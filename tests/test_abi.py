@@ -171,3 +171,47 @@ def test_kernel_constants_exact():
     assert all((s * 5243) >> 17 == s // 25 for s in range(25 * 255 + 1))
     assert all((s * 671089) >> 24 == s // 25 for s in range(25 * 255 + 1)) and 6375 * 671089 < 2 ** 32
     assert all(b * 249 < 65536 for b in range(256))
+
+
+def test_gray_chain_structure_and_limits():
+    st = [("segment", {}), ("segment", {"lo": 100, "hi": 200}), ("segment", {"lo": 5, "hi": 9})]
+    args = [sk.proto([7, 9, 11], sk.U8)] * 2
+    d = sk.Plan(sk.image_chain(st), args).describe()
+    assert d["domain"] == "gray" and [k["stages"] for k in d["kernels"]] == [[0, 3]]
+    d = sk.Plan(sk.image_chain(st), args, {"fusion": sk.FUSE_OFF}).describe()
+    assert [k["stages"] for k in d["kernels"]] == [[0, 1], [1, 2], [2, 3]]
+    d = sk.Plan(sk.image_chain(st), args, {"fusion": sk.FUSE_MASK, "split_mask": 1}).describe()
+    assert [k["stages"] for k in d["kernels"]] == [[0, 1], [1, 3]]
+    # 2^31 voxels and more, including shapes whose product overflows 64 bits
+    for shape in ([1 << 16, 1 << 15], [1 << 40, 1 << 40], [3, 1 << 31]):
+        with pytest.raises(sk.SkelError) as e:
+            sk.Plan(sk.image_chain(st), [sk.proto(shape, sk.U8)] * 2)
+        assert e.value.status == sk.EUNSUPPORTED
+    with pytest.raises(sk.SkelError) as e:      # mixed with image stages
+        sk.Plan(sk.image_chain(st + [("noise", {"seed": 1})]), args)
+    assert e.value.status == sk.ETYPE
+    with pytest.raises(sk.SkelError) as e:      # gray chains have no reduce
+        sk.Plan(sk.image_chain(st, "sum"), args + [sk.proto([1], sk.U64)])
+    assert e.value.status == sk.ETYPE
+    for lo, hi in ((10, 5), (0, 257), (300, 300)):
+        with pytest.raises(sk.SkelError) as e:
+            sk.Map("segment", lo=lo, hi=hi)
+        assert e.value.status == sk.EINVAL
+
+
+def test_fft_chain_structure_and_limits():
+    st = [("fft", {}), ("ifft", {}), ("fft", {})]
+    args = [sk.proto([3, 65536, 2], sk.F32)] * 2
+    d = sk.Plan(sk.image_chain(st), args).describe()
+    assert d["domain"] == "c32" and len(d["kernels"]) == 4        # L + 1 passes when fused
+    d = sk.Plan(sk.image_chain(st), args, {"fusion": sk.FUSE_OFF}).describe()
+    assert len(d["kernels"]) == 6                                  # two passes per stage
+    with pytest.raises(sk.SkelError) as e:                         # 65536-point transforms only
+        sk.Plan(sk.image_chain(st), [sk.proto([3, 4096, 2], sk.F32)] * 2)
+    assert e.value.status in (sk.ESHAPE, sk.EUNSUPPORTED)
+    with pytest.raises(sk.SkelError) as e:
+        sk.Plan(sk.image_chain(st), [sk.proto([65536, 65536, 2], sk.F32)] * 2)
+    assert e.value.status == sk.EUNSUPPORTED
+    with pytest.raises(sk.SkelError) as e:
+        sk.Plan(sk.image_chain(st + [("saxpy", {"a": 1.0})]), args)
+    assert e.value.status == sk.ETYPE
