@@ -85,6 +85,48 @@ def traffic(fetch_csv, write_csv):
             "bytes_per_launch": kf * 1024.0 * sf + kw * 1024.0 * sw}
 
 
+HBM_PEAK_GBS = 8000.0
+NBODY_PEAK_GPAIRS = 256 * 64 * 2.4 / 13.0   # 13 VALU issues per pair
+
+
+def row_work():
+    """(kernel-name key, workload, kind, work per launch) for the kernels that
+    serve one workload each in the whole bench run; kind "hbm": algorithmic
+    bytes, "alu": body pairs."""
+    import synth
+    sides = synth.batch_sides(synth.SEED_BATCH, 256)
+    batch_bytes = sum(2 * s * s * 4 + 4128 for s in sides)
+    fft_bytes = 2 * 512 * 65536 * 8
+    return [
+        ("img_batch_kernel<9, 0, true, true, 2>", "256 uneven requests, config-2 chain", "hbm", batch_bytes),
+        ("fft_pass_kernel<0>", "pass A, 512 x 65536 complex fp32", "hbm", fft_bytes),
+        ("fft_pass_kernel<1>", "fused pass B+A, 512 x 65536 complex fp32", "hbm", fft_bytes),
+        ("fft_pass_kernel<2>", "pass B, 512 x 65536 complex fp32", "hbm", fft_bytes),
+        ("gray_chain_kernel", "Segmentation, 240 x 512 x 512 u8", "hbm", 2 * 240 * 512 * 512),
+        ("nbody_force_kernel<true>", "N-body force + kick-drift, 65536 bodies", "alu", 65536 * 65536),
+        ("nbody_force_kernel<false>", "N-body force only, 65536 bodies", "alu", 65536 * 65536),
+    ]
+
+
+def row_roofline(stats):
+    out = ["", "## Rooflines of the kernels that serve one workload each", "",
+           "Achieved = work per launch / rocprof average duration; peaks: HBM 8 TB/s, N-body 256 CUs x 64 "
+           "lanes x 2.4 GHz / 13 VALU issues per pair.", "",
+           "| kernel | workload | work per launch | avg us | achieved | peak | frac |", "|---|---|---|---|---|---|---|"]
+    for key, what, kind, work in row_work():
+        r = next((x for x in stats if key in x["name"]), None)
+        if r is None:
+            continue
+        sec = r["avg_ns"] * 1e-9
+        if kind == "hbm":
+            ach, peak, unit, wl = work / sec / 1e9, HBM_PEAK_GBS, "GB/s", f"{work} B"
+        else:
+            ach, peak, unit, wl = work / sec / 1e9, NBODY_PEAK_GPAIRS, "G pairs/s", f"{work} pairs"
+        out.append(f"| `{key}` | {what} | {wl} | {r['avg_ns']/1e3:.2f} | {ach:.1f} {unit} | {peak:.1f} | "
+                   f"{ach / peak:.3f} |")
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--trace", required=True)
@@ -127,9 +169,11 @@ def main():
               "Averages mix workloads where one kernel serves several (e.g. the fused image kernel runs the "
               "8192^2 image and, in the sequential baseline of the batch, 256 smaller ones).", "",
               "| kernel | calls | avg us | min us | max us |", "|---|---|---|---|---|"]
-        for r in kernel_stats(a.trace_all):
+        stats_all = kernel_stats(a.trace_all)
+        for r in stats_all:
             al.append(f"| `{r['name'][:90]}` | {r['calls']} | {r['avg_ns']/1e3:.2f} | {r['min_ns']/1e3:.2f} | "
                       f"{r['max_ns']/1e3:.2f} |")
+        al += row_roofline(stats_all)
         open(os.path.join(a.out, "bench_all_kernels.md"), "w").write("\n".join(al) + "\n")
     print(json.dumps(rec))
 
