@@ -386,6 +386,15 @@ skel_status skel_cost_train(const char* db_path, const char* weights_out, int32_
 skel_status skel_cost_select(skel_node root, const skel_buffer* proto, int32_t nargs,
                              const char* weights, skel_plan_opts* chosen);
 
+/* The model as a shortlist for the profiler (the derivation of Sec. 3.2
+ * narrowing what Algorithm 1 has to time): writes the min(k, #valid)
+ * configurations with the lowest predicted runtime to ranked[0..*count), in
+ * increasing predicted time (ranked[0] is skel_cost_select's choice), and the
+ * predicted times in microseconds to pred_us (may be NULL).  ranked and
+ * pred_us are caller-owned arrays of at least k entries; k >= 1. */
+skel_status skel_cost_rank(skel_node root, const skel_buffer* proto, int32_t nargs, const char* weights,
+                           int32_t k, skel_plan_opts* ranked, float* pred_us, int32_t* count);
+
 #ifdef __cplusplus
 }
 #endif

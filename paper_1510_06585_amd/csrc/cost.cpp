@@ -230,10 +230,12 @@ extern "C" skel_status skel_cost_train(const char* db_path, const char* weights_
     return SKEL_OK;
 }
 
-extern "C" skel_status skel_cost_select(skel_node root, const skel_buffer* proto, int32_t nargs, const char* weights,
-                                        skel_plan_opts* chosen) {
-    clear_error();
-    if (!root || !weights || !chosen) return set_error(SKEL_EINVAL, "null argument");
+namespace {
+
+// Every valid configuration of the composition with its predicted run time
+// (log microseconds), from one forward pass of the model over all of them.
+skel_status predict_all(skel_node root, const skel_buffer* proto, int32_t nargs, const char* weights,
+                        std::vector<Config>& cands, std::vector<float>& Y) {
     Model m;
     if (!load_model(weights, m)) return set_error(SKEL_EINVAL, "cannot read cost model %s", weights);
     Linear L;
@@ -242,7 +244,7 @@ extern "C" skel_status skel_cost_select(skel_node root, const skel_buffer* proto
     if (!st && L.dom == DOM_NONE) L.dom = (nargs > 0 && proto[0].dtype == SKEL_U8) ? DOM_U8 : DOM_F32;
     if (!st) st = derive_shape(L, proto, nargs, sh);
     if (st) return st;
-    std::vector<Config> cands = enumerate_configs(L, sh);
+    cands = enumerate_configs(L, sh);
     if (cands.empty()) return set_error(SKEL_EUNSUPPORTED, "no valid configuration");
     const int n = (int)cands.size();
     std::vector<float> X((size_t)n * kNumFeatures);
@@ -258,14 +260,49 @@ extern "C" skel_status skel_cost_select(skel_node root, const skel_buffer* proto
     if (!e) e = hipMemcpy(dP, m.theta.data(), sizeof(float) * kNP, hipMemcpyHostToDevice);
     if (!e) e = hipMemcpy(dX, X.data(), sizeof(float) * X.size(), hipMemcpyHostToDevice);
     if (!e) e = launch_mlp_forward(dP, dX, n, dY, nullptr);
-    std::vector<float> Y(n);
+    Y.assign(n, 0.0f);
     if (!e) e = hipMemcpy(Y.data(), dY, sizeof(float) * n, hipMemcpyDeviceToHost);
     for (void* q : {(void*)dP, (void*)dX, (void*)dY})
         if (q) hipFree(q);
     if (e != hipSuccess) return set_error(SKEL_EDEVICE, "cost model inference: %s", hipGetErrorString(e));
+    return SKEL_OK;
+}
+
+}  // namespace
+
+extern "C" skel_status skel_cost_select(skel_node root, const skel_buffer* proto, int32_t nargs, const char* weights,
+                                        skel_plan_opts* chosen) {
+    clear_error();
+    if (!root || !weights || !chosen) return set_error(SKEL_EINVAL, "null argument");
+    std::vector<Config> cands;
+    std::vector<float> Y;
+    skel_status st = predict_all(root, proto, nargs, weights, cands, Y);
+    if (st) return st;
     int best = 0;
-    for (int i = 1; i < n; ++i)
+    for (int i = 1; i < (int)Y.size(); ++i)
         if (Y[i] < Y[best]) best = i;
     config_to_opts(cands[best], chosen);
+    return SKEL_OK;
+}
+
+extern "C" skel_status skel_cost_rank(skel_node root, const skel_buffer* proto, int32_t nargs, const char* weights,
+                                      int32_t k, skel_plan_opts* ranked, float* pred_us, int32_t* count) {
+    clear_error();
+    if (!root || !weights || !ranked || !count || k < 1) return set_error(SKEL_EINVAL, "null argument or k < 1");
+    *count = 0;
+    std::vector<Config> cands;
+    std::vector<float> Y;
+    skel_status st = predict_all(root, proto, nargs, weights, cands, Y);
+    if (st) return st;
+    std::vector<int> idx(Y.size());
+    for (size_t i = 0; i < idx.size(); ++i) idx[i] = (int)i;
+    // ties keep enumeration order, so the first entry is skel_cost_select's choice
+    std::stable_sort(idx.begin(), idx.end(), [&](int a, int b) { return Y[a] < Y[b]; });
+    const int n = std::min<int>(k, (int)idx.size());
+    for (int i = 0; i < n; ++i) {
+        config_to_opts(cands[idx[i]], &ranked[i]);
+        if (pred_us) pred_us[i] = std::exp(Y[idx[i]]);
+    }
+    *count = n;
     return SKEL_OK;
 }

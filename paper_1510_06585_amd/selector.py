@@ -13,7 +13,9 @@ plan and tile configuration for compositions it has never seen:
    auto-tuner (labels), and every configuration of every held-out composition
    (exhaustive: its best is the reference);
 3. train the MLP on the GPU (skel_cost_train) and let it pick a configuration
-   for each held-out composition (skel_cost_select);
+   for each held-out composition (skel_cost_select), or shortlist its k best
+   (skel_cost_rank) for the profiler to time (scored here as the fastest
+   measured of the k);
 4. report the regret t(chosen) / t(best) - 1 next to the baselines: the
    default plan, nearest-neighbour derivation over the training rows, the
    untrained network, a random configuration, and the paper's own search
@@ -170,8 +172,8 @@ def experiment(n_train: int = 1000, n_test: int = 200, per_train: int = 20, seed
     mu, sd = F.mean(0), F.std(0)
     sd[sd < 1e-6] = 1.0
     Fz = (F - mu) / sd
-    reg = {"model": [], "default": [], "nearest_neighbour": [], "untrained": [], "random": [],
-           "pruned_tuner": []}
+    reg = {"model": [], "model_top3_timed": [], "model_top5_timed": [], "default": [], "nearest_neighbour": [],
+           "untrained": [], "random": [], "pruned_tuner": []}
     for c, rows, tdef, (popts, _) in zip(test, test_rows, defaults, pruned):
         root = sk.image_chain(c["stages"], c["reduce"])
         protos = _args_for_proto(c)
@@ -180,6 +182,12 @@ def experiment(n_train: int = 1000, n_test: int = 200, per_train: int = 20, seed
             o = sk.cost_select(root, protos, w)
             t = _match(rows, o)
             reg[name].append((t if t is not None else tdef) / best - 1.0)
+        # the model's shortlist timed by the profiler: the fastest measured of
+        # its k best-predicted configurations (k timings per composition)
+        ranked = sk.cost_rank(root, protos, weights, 5)
+        for k in (3, 5):
+            ts = [t for t in (_match(rows, o) for o, _ in ranked[:k]) if t is not None]
+            reg[f"model_top{k}_timed"].append((min(ts) if ts else tdef) / best - 1.0)
         reg["default"].append(tdef / best - 1.0)
         q = (np.stack([r["f"] for r in rows]) - mu) / sd
         d2 = ((q[:, None, :] - Fz[None, :, :]) ** 2).sum(-1)

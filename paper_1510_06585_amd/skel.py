@@ -115,6 +115,9 @@ _SIGS = {
                                          ctypes.POINTER(ctypes.c_float), ctypes.POINTER(ctypes.c_float)]),
     "skel_cost_select": (ctypes.c_int32, [_node_p, ctypes.POINTER(Buffer), ctypes.c_int32, ctypes.c_char_p,
                                           ctypes.POINTER(PlanOpts)]),
+    "skel_cost_rank": (ctypes.c_int32, [_node_p, ctypes.POINTER(Buffer), ctypes.c_int32, ctypes.c_char_p,
+                                        ctypes.c_int32, ctypes.POINTER(PlanOpts), ctypes.POINTER(ctypes.c_float),
+                                        ctypes.POINTER(ctypes.c_int32)]),
 }
 EXPORTS = tuple(_SIGS)
 
@@ -437,6 +440,17 @@ def cost_select(root: Node, protos, weights: str) -> dict:
     o = PlanOpts()
     _check(lib().skel_cost_select(root.handle, arr, n, weights.encode(), ctypes.byref(o)))
     return o.as_dict()
+
+
+def cost_rank(root: Node, protos, weights: str, k: int):
+    """The k configurations with the lowest predicted runtime (skel_cost_rank):
+    a list of (options, predicted microseconds), best first."""
+    arr, n = _buf_array(protos)
+    out = (PlanOpts * max(1, k))()
+    pred = (ctypes.c_float * max(1, k))()
+    cnt = ctypes.c_int32()
+    _check(lib().skel_cost_rank(root.handle, arr, n, weights.encode(), k, out, pred, ctypes.byref(cnt)))
+    return [(out[i].as_dict(), float(pred[i])) for i in range(cnt.value)]
 
 
 # --------------------------------------------------------------- helpers

@@ -142,3 +142,16 @@ def test_cost_train_and_select_on_synthetic_law(tmp_path):
     d = sk.Plan(comp_root, proto, o).describe()
     assert len(d["kernels"]) == 1
     assert os.path.getsize(w) > 1000
+    # the ranked shortlist: best first, distinct, increasing predicted time,
+    # led by cost_select's choice, and capped by the number of valid configs
+    ranked = sk.cost_rank(comp_root, proto, w, 6)
+    assert len(ranked) == 6 and ranked[0][0] == o
+    preds = [p for _, p in ranked]
+    assert all(a <= b for a, b in zip(preds, preds[1:])) and preds[0] > 0
+    keys = {tuple(sorted(r.items())) for r, _ in ranked}
+    assert len(keys) == 6
+    n_valid = sk.config_count(comp_root, proto)
+    everything = sk.cost_rank(comp_root, proto, w, n_valid + 10)
+    assert len(everything) == n_valid
+    with pytest.raises(sk.SkelError):
+        sk.cost_rank(comp_root, proto, w, 0)
