@@ -67,6 +67,7 @@ bool save_model(const char* path, const Model& m) {
 
 // One database row: key, 6 config fields, 24 features, median us, min us.
 bool parse_row(const std::string& line, std::vector<float>& feat, float& t_us) {
+    if (line.empty() || line[0] == '#') return false;   // provenance comments
     std::vector<std::string> tok;
     std::stringstream ss(line);
     std::string x;

@@ -11,6 +11,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <ctime>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -274,6 +275,24 @@ void db_row(FILE* db, const std::string& key, const Linear& L, const Shape& sh, 
     fprintf(db, ",%.4f,%.4f\n", med, mn);
 }
 
+// Provenance of the rows that follow (the knowledge base of Sec. 3.2 keeps
+// profiles across sessions and machines): one comment line per tuning session
+// with the tuner, the device, the runtime version and the UTC time.  Readers
+// skip lines that start with '#'.
+void db_session(FILE* db, const char* tuner, const std::string& key) {
+    int dev = 0, rt = 0;
+    hipDeviceProp_t prop;
+    memset(&prop, 0, sizeof(prop));
+    if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess) prop.gcnArchName[0] = 0;
+    if (hipRuntimeGetVersion(&rt) != hipSuccess) rt = 0;
+    char when[32] = "unknown";
+    const time_t now = time(nullptr);
+    struct tm g;
+    if (gmtime_r(&now, &g)) strftime(when, sizeof(when), "%Y-%m-%dT%H:%M:%SZ", &g);
+    fprintf(db, "# skel tuning session: tuner=%s composition=%s device=%s cus=%d hip_runtime=%d utc=%s\n", tuner,
+            key.c_str(), prop.gcnArchName[0] ? prop.gcnArchName : "unknown", prop.multiProcessorCount, rt, when);
+}
+
 }  // namespace
 
 extern "C" skel_status skel_tune(skel_node root, const skel_buffer* args, int32_t nargs, const char* db_path,
@@ -307,6 +326,7 @@ extern "C" skel_status skel_tune(skel_node root, const skel_buffer* args, int32_
         if (!db) return set_error(SKEL_EINVAL, "cannot open %s", db_path);
     }
     const std::string key = composition_key(L, sh);
+    if (db) db_session(db, "exhaustive", key);
     Timer T;
     if ((st = T.init())) {
         if (db) fclose(db);
@@ -442,6 +462,7 @@ extern "C" skel_status skel_tune_pruned(skel_node root, const skel_buffer* args,
         if (!db) return set_error(SKEL_EINVAL, "cannot open %s", db_path);
     }
     const std::string key = composition_key(L, sh);
+    if (db) db_session(db, "pruned", key);
     Timer T;
     if ((st = T.init())) {
         if (db) fclose(db);

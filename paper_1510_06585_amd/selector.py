@@ -17,7 +17,8 @@ plan and tile configuration for compositions it has never seen:
    (skel_cost_rank) for the profiler to time (scored here as the fastest
    measured of the k);
 4. report the regret t(chosen) / t(best) - 1 next to the baselines: the
-   default plan, nearest-neighbour derivation over the training rows, the
+   default plan, nearest-neighbour and radial-basis-weighted derivation over
+   the training rows (the paper's interpolation over stored profiles), the
    untrained network, a random configuration, and the paper's own search
    (Algorithm 1, skel_tune_pruned) with the number of configurations it times.
 
@@ -65,6 +66,8 @@ def _read_rows(path):
     if not os.path.exists(path):
         return rows
     for line in open(path):
+        if line.startswith("#"):      # provenance of a tuning session
+            continue
         t = line.rstrip("\n").split(",")
         if len(t) != _DB_FEAT0 + 24 + 2:
             continue
@@ -173,7 +176,7 @@ def experiment(n_train: int = 1000, n_test: int = 200, per_train: int = 20, seed
     sd[sd < 1e-6] = 1.0
     Fz = (F - mu) / sd
     reg = {"model": [], "model_top3_timed": [], "model_top5_timed": [], "default": [], "nearest_neighbour": [],
-           "untrained": [], "random": [], "pruned_tuner": []}
+           "rbf": [], "untrained": [], "random": [], "pruned_tuner": []}
     for c, rows, tdef, (popts, _) in zip(test, test_rows, defaults, pruned):
         root = sk.image_chain(c["stages"], c["reduce"])
         protos = _args_for_proto(c)
@@ -193,6 +196,16 @@ def experiment(n_train: int = 1000, n_test: int = 200, per_train: int = 20, seed
         d2 = ((q[:, None, :] - Fz[None, :, :]) ** 2).sum(-1)
         pred = T[d2.argmin(1)]
         reg["nearest_neighbour"].append(rows[int(pred.argmin())]["t"] / best - 1.0)
+        # radial-basis-weighted derivation: Gaussian-kernel average of the log
+        # times of the 32 nearest training rows, bandwidth the squared
+        # distance of the 8th nearest
+        kn = min(32, d2.shape[1])
+        idx = np.argpartition(d2, kn - 1, axis=1)[:, :kn]
+        dk = np.take_along_axis(d2, idx, 1)
+        h2 = np.sort(dk, 1)[:, min(7, kn - 1)][:, None] + 1e-12
+        w = np.exp(-dk / h2)
+        predr = (w * T[idx]).sum(1) / w.sum(1)
+        reg["rbf"].append(rows[int(predr.argmin())]["t"] / best - 1.0)
         reg["random"].append(rows[int(rng.integers(0, len(rows)))]["t"] / best - 1.0)
         t = _match(rows, popts)
         reg["pruned_tuner"].append((t if t is not None else tdef) / best - 1.0)

@@ -20,8 +20,11 @@ def test_tune_image_chain(tmp_path):
     root = sk.image_chain(st, "hist_sum")
     db = str(tmp_path / "db.csv")
     best, us = sk.tune(root, args, db, reps=3)
-    assert sk.config_count(root, args) == len(open(db).readlines())
-    rows = [l.strip().split(",") for l in open(db)]
+    lines = open(db).readlines()
+    # one provenance line for the session, then one row per configuration
+    assert lines[0].startswith("# skel tuning session: tuner=exhaustive") and "device=gfx950" in lines[0]
+    rows = [l.strip().split(",") for l in lines if not l.startswith("#")]
+    assert sk.config_count(root, args) == len(rows) == len(lines) - 1
     assert len(rows) >= 8 and us > 0
     times = [float(r[-2]) for r in rows]
     assert min(times) == pytest.approx(us, rel=1e-6)
@@ -59,11 +62,12 @@ def test_tune_pruned_walks_ordered_dimensions(tmp_path):
     root = sk.image_chain(st, "hist_sum")
     db = str(tmp_path / "pruned.csv")
     best, us, timed = sk.tune_pruned(root, args, db, reps=3)
-    rows = [l.strip().split(",") for l in open(db)]
+    assert open(db).readline().startswith("# skel tuning session: tuner=pruned")
+    rows = [l.strip().split(",") for l in open(db) if not l.startswith("#")]
     assert timed == len(rows) and 1 <= timed <= sk.config_count(root, args)
     full = str(tmp_path / "full.csv")
     sk.tune(root, args, full, reps=1)
-    cands = {tuple(r[1:7]) for r in (l.strip().split(",") for l in open(full))}
+    cands = {tuple(r[1:7]) for r in (l.strip().split(",") for l in open(full) if not l.startswith("#"))}
     assert all(tuple(r[1:7]) in cands for r in rows)
     assert float(rows[0][7 + 10]) == 1.0                  # feature 10 (kernels) of the first timed config
     assert min(float(r[-2]) for r in rows) == pytest.approx(us, rel=1e-6)
