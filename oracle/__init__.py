@@ -6,15 +6,18 @@ Only ``tests/``, ``__graft_entry__.smoke()`` and the ``cpu_baseline`` leg of
 
 Every skeleton is executed stage by stage, each stage reading a whole input
 and materialising a whole output: the depth-first, one-kernel-at-a-time
-single-device execution of a skeleton computational tree (Sec. 2 of the
-paper, "Overview of the Marrow Algorithmic Framework").  The per-stage
-arithmetic lives in ``oracle.c`` (plain C loops) and, for the cost-model MLP,
-in ``oracle/mlp.py`` (numpy, fp64).
+single-device execution of a skeleton computational tree (the overview of
+the framework in Sec. 2).  The per-stage arithmetic of the image, vector and
+N-body stages lives in ``oracle.c`` (plain C loops); the cost-model MLP is in
+``oracle/mlp.py`` (numpy, fp64); Segmentation is written out in numpy below
+and the FFT stages use numpy's FFT in complex128 as their step.
 
 Stage descriptions used here are plain tuples ``(name, params)`` with names
 ``"noise"`` (params ``{"seed": int}``), ``"solarise"``, ``"mirror"``,
 ``"blur5"`` and, for fp32 vectors, ``"saxpy"`` (params ``{"a": float}``, plus
-one side vector per saxpy stage) and ``"mirror"`` (reversal).
+one side vector per saxpy stage) and ``"mirror"`` (reversal).  Segmentation
+chains are lists of ``(lo, hi)`` threshold pairs and FFT chains lists of
+``"fft"`` / ``"ifft"``.
 """
 from __future__ import annotations
 
@@ -203,8 +206,8 @@ def segment(vol: np.ndarray, lo: int = SEGMENT_LO, hi: int = SEGMENT_HI) -> np.n
 
 
 def run_segment_chain(vol: np.ndarray, stages) -> np.ndarray:
-    """Pipeline of Segmentation stages, each materialised: stages are
-    (lo, hi) pairs, (0, 0) for the default thresholds."""
+    """Pipeline (Sec. 2) of Segmentation stages, each materialised: stages
+    are (lo, hi) pairs, (0, 0) for the default thresholds."""
     cur = np.asarray(vol)
     for lo, hi in stages:
         cur = segment(cur, lo, hi) if (lo or hi) else segment(cur)
