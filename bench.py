@@ -7,10 +7,10 @@ resident in HBM.  Prints ONE JSON line with throughput (Gelem/s = Gpixel/s),
 the roofline of the dominant kernel measured live with HIP events, the CPU
 oracle's throughput on the host, the fused-vs-plain speedup and, under
 "extras", the other skeletons (plain filter pipeline, N-body Loop, batched
-requests).
+requests, while Loop, FFT pipeline, Segmentation).
 
   python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-extras]
-                  [--no-cpu-baseline] [--selector]
+                  [--no-cpu-baseline] [--selector] [--profile-run] [--config1-only]
 """
 from __future__ import annotations
 
@@ -93,9 +93,9 @@ class HipEvents:
             self.hip.hipEventDestroy(self.ct.c_void_p(e))
 
 
-def kernel_ms(plan, bound, kernel, steps):
-    """Average duration of one kernel of a plan, from HIP events the plan
-    records around that kernel on the launch stream."""
+def kernel_times(plan, bound, kernel, steps):
+    """Durations (ms) of one kernel of a plan over `steps` runs, from HIP
+    events the plan records around that kernel on the launch stream."""
     import torch
     ev = HipEvents(steps)
     for i in range(steps):
@@ -103,9 +103,15 @@ def kernel_ms(plan, bound, kernel, steps):
         plan.run(bound)
     torch.cuda.synchronize()
     plan.kernel_events(-1)
-    ms = sum(ev.ms(i) for i in range(steps)) / steps
+    ts = [ev.ms(i) for i in range(steps)]
     ev.close()
-    return ms
+    return ts
+
+
+def kernel_ms(plan, bound, kernel, steps):
+    """Average duration of one kernel of a plan (see kernel_times)."""
+    ts = kernel_times(plan, bound, kernel, steps)
+    return sum(ts) / len(ts)
 
 
 def traffic_for(kernel: str, algo_bytes: float):
@@ -121,11 +127,23 @@ def traffic_for(kernel: str, algo_bytes: float):
     return rec["bytes_per_launch"]
 
 
+def _cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(img, budget_s=12.0):
     """The oracle as it stands on the host's cores: the full chain over the
-    full 8192 x 8192 image, every stage materialised, repeated for ~budget_s."""
+    full 8192 x 8192 image, every stage materialised, repeated for ~budget_s;
+    then one run of the same chain on one thread."""
     import oracle
     oracle.lib()
+    cores = oracle.max_threads()
     reps, t = 0, 0.0
     while reps < 2 or t < budget_s:
         t0 = time.perf_counter()
@@ -133,11 +151,18 @@ def cpu_baseline(img, budget_s=12.0):
         t += time.perf_counter() - t0
         reps += 1
     px = img.shape[0] * img.shape[1]
-    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    oracle.set_threads(1)
+    t0 = time.perf_counter()
+    oracle.run_image_pipeline(img, CFG2, "hist_sum")
+    t1 = time.perf_counter() - t0
+    oracle.set_threads(cores)
     return {"value": round(px * reps / t / 1e9, 6), "unit": "Gelem/s", "cores": cores, "kind": "oracle",
             "sample": f"full 8192x8192 image x {reps} runs (noise, solarise, blur5, mirror each materialised, "
                       f"then histogram + sums); OpenMP over rows in noise/blur, other stages single-threaded",
-            "seconds": round(t, 3)}
+            "seconds": round(t, 3),
+            "single_thread": {"value": round(px / t1 / 1e9, 6), "unit": "Gelem/s", "sample": "the same chain, "
+                              "one run on one thread", "seconds": round(t1, 3)},
+            "host": {"cpu": _cpu_model(), "nproc": os.cpu_count()}}
 
 
 def image_args(img, reduce="hist_sum"):
@@ -162,7 +187,8 @@ def bench_config2(steps, warmup, do_cpu):
     plain = sk.Plan(root, args, {"fusion": sk.FUSE_OFF})
     wall, ev_ms = timed_runs(lambda: fused.run(bound), steps, warmup)
     ms_step = wall * 1e3 / steps
-    k_ms = kernel_ms(fused, bound, 0, steps)
+    k_ts = sorted(kernel_times(fused, bound, 0, steps))
+    k_ms = sum(k_ts) / len(k_ts)
     _, plain_ms = timed_runs(lambda: plain.run(bound), max(5, steps // 4), 3)
     plain_ms /= max(5, steps // 4)
     # Context: a device-to-device copy of the same image through torch.
@@ -193,7 +219,8 @@ def bench_config2(steps, warmup, do_cpu):
                    "wg": desc["kernels"][0].get("wg")},
         "roofline": {"bound": "hbm", "kernel": kname, "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": traffic, "kernel_ms": round(k_ms, 5), "algorithmic_bytes": int(algo)},
+                     "traffic": traffic, "kernel_ms": round(k_ms, 5), "kernel_ms_min": round(k_ts[0], 5),
+                     "kernel_ms_median": round(k_ts[len(k_ts) // 2], 5), "algorithmic_bytes": int(algo)},
         "copy_reference_gbs": round(copy_gbs, 1),
         "event_ms_per_step": round(ev_ms / steps, 5),
         "plain_ms_per_step": round(plain_ms, 5),
@@ -419,6 +446,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--selector", action="store_true", help="run the learned-selector experiment instead")
     ap.add_argument("--profile-run", action="store_true", help="short run for rocprofv3 counter passes")
+    ap.add_argument("--config1-only", action="store_true",
+                    help="only the 1024x1024 filter pipeline, plain and fused (for a per-stage kernel trace)")
     ap.add_argument("--selector-dir", default=None, help="where the selector experiment keeps its databases")
     ap.add_argument("--selector-train", type=int, default=1000)
     ap.add_argument("--selector-test", type=int, default=200)
@@ -436,6 +465,9 @@ def main():
     sk.lib()
     if a.profile_run:
         profile_run(a.steps)
+        return
+    if a.config1_only:
+        print(json.dumps(bench_config1()), flush=True)
         return
     if a.selector:
         from paper_1510_06585_amd import selector

@@ -56,6 +56,8 @@ def lib():
         if not os.path.exists(_SO):
             build(force=False)
         L = ctypes.CDLL(_SO)
+        L.orc_set_threads.argtypes = [ctypes.c_int]
+        L.orc_max_threads.restype = ctypes.c_int
         L.orc_fmix32.restype = ctypes.c_uint32
         L.orc_fmix32.argtypes = [ctypes.c_uint32]
         L.orc_noise_offset.restype = ctypes.c_int
@@ -75,6 +77,15 @@ def lib():
                                     ctypes.c_double, ctypes.c_double]
         _lib = L
     return _lib
+
+
+def set_threads(n: int) -> None:
+    """Threads of the oracle's parallel loops (results do not depend on it)."""
+    lib().orc_set_threads(int(n))
+
+
+def max_threads() -> int:
+    return int(lib().orc_max_threads())
 
 
 def _p(a: np.ndarray, t):

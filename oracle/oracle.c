@@ -20,6 +20,7 @@
 #include <math.h>
 #include <stdint.h>
 #include <stdlib.h>
+#include <omp.h>
 
 /* ---------------------------------------------------------------------------
  * Noise stage (Sec. 4, Filter Pipeline, first filter).  The paper names a
@@ -188,3 +189,7 @@ int orc_nbody_run(double* pos, double* vel, int64_t N, int steps, double G, doub
     free(acc);
     return 0;
 }
+
+/* Thread count of the parallel loops (results do not depend on it). */
+void orc_set_threads(int n) { omp_set_num_threads(n > 0 ? n : 1); }
+int orc_max_threads(void) { return omp_get_max_threads(); }

@@ -85,6 +85,8 @@ def traffic(fetch_csv, write_csv):
             "bytes_per_launch": kf * 1024.0 * sf + kw * 1024.0 * sw}
 
 
+COMMAND_CONFIG1 = ("rocprofv3 --kernel-trace --stats -d DIR -o cfg1 --output-format csv -- python3 bench.py "
+                   "--config1-only")
 HBM_PEAK_GBS = 8000.0
 NBODY_PEAK_GPAIRS = 256 * 64 * 2.4 / 13.0   # 13 VALU issues per pair
 
@@ -129,14 +131,29 @@ def row_roofline(stats):
 
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("--trace", required=True)
-    ap.add_argument("--fetch", required=True)
-    ap.add_argument("--write", required=True)
+    ap.add_argument("--trace")
+    ap.add_argument("--fetch")
+    ap.add_argument("--write")
     ap.add_argument("--sq")
     ap.add_argument("--trace-all", help="kernel stats of the whole bench run (every skeleton)")
+    ap.add_argument("--trace-config1", help="kernel stats of the config-1 run alone (per-stage times)")
     ap.add_argument("--out", required=True)
     a = ap.parse_args()
     os.makedirs(a.out, exist_ok=True)
+    if a.trace_config1:
+        c1 = ["# rocprofv3 summary: filter pipeline 1024x1024 RGBA u8 (noise > solarise > mirror), plain plan "
+              "(one kernel per stage) and fused plan, 220 runs each", "",
+              "Command (repository root on the GPU box, TMPDIR=/tmp):", "", "```", COMMAND_CONFIG1, "```", "",
+              "Kernels: `img_band_kernel<1, 0, false, false, 0>` is the noise stage, `<2, 0, false, false, 0>` "
+              "solarise, `<0, 0, false, false, 2>` mirror (a copy with the store flipped), "
+              "`<9, 0, false, false, 2>` the fused chain.", "",
+              "| kernel | calls | avg us | min us | max us |", "|---|---|---|---|---|"]
+        for r in kernel_stats(a.trace_config1):
+            c1.append(f"| `{r['name'][:90]}` | {r['calls']} | {r['avg_ns']/1e3:.2f} | {r['min_ns']/1e3:.2f} | "
+                      f"{r['max_ns']/1e3:.2f} |")
+        open(os.path.join(a.out, "img_filter_pipeline_1024.md"), "w").write("\n".join(c1) + "\n")
+    if not (a.trace and a.fetch and a.write):
+        return
     st = kernel_stats(a.trace)
     tr = traffic(a.fetch, a.write)
     src = os.path.join(HERE, "csrc", "kern_img.hip")
