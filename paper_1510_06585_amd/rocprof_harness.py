@@ -87,6 +87,8 @@ def traffic(fetch_csv, write_csv):
 
 COMMAND_CONFIG1 = ("rocprofv3 --kernel-trace --stats -d DIR -o cfg1 --output-format csv -- python3 bench.py "
                    "--config1-only")
+COMMAND_MLP = ("rocprofv3 --pmc SQ_INSTS_VALU_MFMA_MOPS_F32 SQ_VALU_MFMA_BUSY_CYCLES SQ_INSTS_VALU SQ_BUSY_CYCLES "
+               "-d DIR -o mfma --output-format csv -- python3 -m paper_1510_06585_amd.mlp_probe")
 HBM_PEAK_GBS = 8000.0
 NBODY_PEAK_GPAIRS = 256 * 64 * 2.4 / 13.0   # 13 VALU issues per pair
 
@@ -137,6 +139,7 @@ def main():
     ap.add_argument("--sq")
     ap.add_argument("--trace-all", help="kernel stats of the whole bench run (every skeleton)")
     ap.add_argument("--trace-config1", help="kernel stats of the config-1 run alone (per-stage times)")
+    ap.add_argument("--mlp-counters", help="MFMA counter pass over the cost-model MLP kernels")
     ap.add_argument("--out", required=True)
     a = ap.parse_args()
     os.makedirs(a.out, exist_ok=True)
@@ -152,6 +155,26 @@ def main():
             c1.append(f"| `{r['name'][:90]}` | {r['calls']} | {r['avg_ns']/1e3:.2f} | {r['min_ns']/1e3:.2f} | "
                       f"{r['max_ns']/1e3:.2f} |")
         open(os.path.join(a.out, "img_filter_pipeline_1024.md"), "w").write("\n".join(c1) + "\n")
+    if a.mlp_counters:
+        cm = counters(a.mlp_counters)
+        n = 16384
+        fwd_flops = 2 * n * (24 * 64 + 64 * 64 + 64)
+        ml = ["# rocprofv3 counters: cost-model MLP kernels on the matrix cores (16384 samples, 24->64->64->1)", "",
+              "Command (repository root on the GPU box, TMPDIR=/tmp):", "", "```", COMMAND_MLP, "```", "",
+              "The script runs `skel_mlp_forward` and `skel_mlp_grad` three times each on 16384 random "
+              f"samples.  The forward pass's layer products are {fwd_flops} flops; one "
+              "SQ_INSTS_VALU_MFMA_MOPS_F32 count is 512 flops.", "",
+              "| kernel | counter | mean per dispatch |", "|---|---|---|"]
+        for kern in sorted(cm):
+            if "mlp" not in kern:
+                continue
+            short = kern.split("(")[0].replace("skel::", "")
+            for c, v in sorted(cm[kern].items()):
+                ml.append(f"| `{short}` | {c} | {v:.0f} |")
+            mops = cm[kern].get("SQ_INSTS_VALU_MFMA_MOPS_F32", 0.0)
+            if mops:
+                ml.append(f"| `{short}` | MFMA flops (MOPS x 512) | {mops * 512:.0f} |")
+        open(os.path.join(a.out, "mlp_mfma_16384.md"), "w").write("\n".join(ml) + "\n")
     if not (a.trace and a.fetch and a.write):
         return
     st = kernel_stats(a.trace)
