@@ -445,16 +445,16 @@ static int final_value_bins(const Linear& L) {
     return 256;
 }
 
+// Compute units of the current device, read once (a function-local static is
+// initialised exactly once even when plans are compiled from several threads).
 int device_cu_count() {
-    static int cus = 0;
-    if (!cus) {
+    static const int cus = [] {
         int dev = 0, n = 0;
         if (hipGetDevice(&dev) == hipSuccess &&
             hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && n > 0)
-            cus = n;
-        else
-            cus = 256;
-    }
+            return n;
+        return 256;
+    }();
     return cus;
 }
 
