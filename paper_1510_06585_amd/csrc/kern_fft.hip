@@ -137,14 +137,18 @@ static __device__ __forceinline__ void dft16(cpx (&v)[16]) {
 // same, so a second transform of the same rows (the fused pass) starts from
 // the registers.  S is the LDS tile used for the transposition in between;
 // the call starts with a barrier (other threads may still read S) and ends
-// without one.
-template <int DIR>
-static __device__ __forceinline__ void dft256_reg(cpx* S, const TwLds& T, cpx (&v)[16]) {
+// without one.  The thread's twiddles W_256^(u p), p = 1..15, come from the
+// LDS table, or with SHARED from w[p] = (cos, sin)(2 pi u p / 256): read once
+// by the fused pass and used by both of its transforms.
+template <int DIR, bool SHARED>
+static __device__ __forceinline__ void dft256_reg(cpx* S, const TwLds& T, const cpx (&w)[16], cpx (&v)[16]) {
     const int j = threadIdx.x >> 4, u = threadIdx.x & 15;
     // m = a + 16 c with a = u: 16-point DFT over c, twiddle W_256^(a p).
     dft16<DIR>(v);
 #pragma unroll
-    for (int p = 1; p < 16; ++p) v[p] = cmul(v[p], tw<DIR>(T, (uint32_t)(u * p) * (kFftN / kFftR)));
+    for (int p = 1; p < 16; ++p)
+        v[p] = cmul(v[p], SHARED ? cpx{w[p].x, DIR < 0 ? -w[p].y : w[p].y}
+                                 : tw<DIR>(T, (uint32_t)(u * p) * (kFftN / kFftR)));
     __syncthreads();
 #pragma unroll
     for (int p = 0; p < 16; ++p) S[sx(j, 16 * p + u)] = v[p];   // Z[a = u][p] at 16 p + a
@@ -155,11 +159,13 @@ static __device__ __forceinline__ void dft256_reg(cpx* S, const TwLds& T, cpx (&
     dft16<DIR>(v);
 }
 
-static __device__ __forceinline__ void dft256_reg(cpx* S, const TwLds& T, cpx (&v)[16], int dir) {
+template <bool SHARED>
+static __device__ __forceinline__ void dft256_reg(cpx* S, const TwLds& T, const cpx (&w)[16], cpx (&v)[16],
+                                                  int dir) {
     if (dir < 0)
-        dft256_reg<-1>(S, T, v);
+        dft256_reg<-1, SHARED>(S, T, w, v);
     else
-        dft256_reg<1>(S, T, v);
+        dft256_reg<1, SHARED>(S, T, w, v);
 }
 
 // Twiddle W_N^(n1 k2) (n1 = kFftCols g + j, k2 = m) and store T[k2][n1].
@@ -211,7 +217,11 @@ __global__ void __launch_bounds__(kFftThreads) fft_pass_kernel(const FftArgs A) 
         __syncthreads();   // the twiddle tables
     }
     {
-        dft256_reg(S, W, v, A.dir1);
+        cpx w[16];
+        if (MODE == 1)
+#pragma unroll
+            for (int p = 1; p < 16; ++p) w[p] = W.hi[(u * p) & 255];   // W^(256 u p) = W_256^(u p)
+        dft256_reg<MODE == 1>(S, W, w, v, A.dir1);
         if (MODE == 1) {
             // v[q] = X[k2 + 256 k1] of the first stage at k1 = u + 16 q (k2 =
             // kFftCols g + j): the second stage's input at n1' = k2, n2' = k1,
@@ -219,7 +229,7 @@ __global__ void __launch_bounds__(kFftThreads) fft_pass_kernel(const FftArgs A) 
             if (A.scale1 != 1.0f)
 #pragma unroll
                 for (int q = 0; q < 16; ++q) v[q] = {v[q].x * A.scale1, v[q].y * A.scale1};
-            dft256_reg(S, W, v, A.dir2);
+            dft256_reg<true>(S, W, w, v, A.dir2);
         }
         __syncthreads();
 #pragma unroll
