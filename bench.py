@@ -390,6 +390,47 @@ def bench_fft():
     return res
 
 
+def bench_saxpy():
+    """Saxpy (Sec. 4) at the paper's largest size, 5 x 10^7 fp32 elements: one
+    stage (read v and w, write out: 12 bytes per element), and a MapReduce of
+    two stages with an fp32 sum, fused (one pass, 16 bytes per element) vs
+    one kernel per stage."""
+    import torch
+    import paper_1510_06585_amd as sk
+    import synth
+    n = 50_000_000
+    rng = __import__("numpy").random.default_rng(synth.SEED_SELECT)
+    a1, a2 = synth.saxpy_coeff(rng), synth.saxpy_coeff(rng)
+    x = torch.from_numpy(synth.vector(11, n)).cuda()
+    w1 = torch.from_numpy(synth.vector(12, n)).cuda()
+    w2 = torch.from_numpy(synth.vector(13, n)).cuda()
+    out = torch.empty_like(x)
+    s = torch.zeros(1, device="cuda")
+    res = {"elements": n}
+    one = sk.Plan(sk.Map("saxpy", a=a1), [x, w1, out])
+    b1 = sk.bind([x, w1, out])
+    _, ms = timed_runs(lambda: one.run(b1), 200, 50)
+    ms /= 200
+    res["one_stage_ms"] = round(ms, 4)
+    res["one_stage_hbm_gbs"] = round(12.0 * n / (ms * 1e-3) / 1e9, 1)
+    res["one_stage_hbm_frac"] = round(res["one_stage_hbm_gbs"] / HBM_PEAK_GBS, 4)
+    one.destroy()
+    root = sk.image_chain([("saxpy", {"a": a1}), ("saxpy", {"a": a2})], "sum")
+    args = [x, w1, w2, out, s]
+    for name, opt in (("chain2_sum_fused", {}), ("chain2_sum_plain", {"fusion": sk.FUSE_OFF})):
+        p = sk.Plan(root, args, opt)
+        b = sk.bind(args)
+        _, ms = timed_runs(lambda: p.run(b), 200, 50)
+        ms /= 200
+        res[f"{name}_ms"] = round(ms, 4)
+        res[f"{name}_kernels"] = len(p.describe()["kernels"])
+        p.destroy()
+    res["chain2_sum_fused_hbm_gbs"] = round(16.0 * n / (res["chain2_sum_fused_ms"] * 1e-3) / 1e9, 1)
+    res["chain2_sum_fused_hbm_frac"] = round(res["chain2_sum_fused_hbm_gbs"] / HBM_PEAK_GBS, 4)
+    res["chain2_sum_fused_vs_plain_speedup"] = round(res["chain2_sum_plain_ms"] / res["chain2_sum_fused_ms"], 3)
+    return res
+
+
 def bench_segment():
     """Segmentation (Map over a gray volume, Sec. 4) at the paper's largest
     size, 60 MiB (240 x 512 x 512 voxels): one stage, and a chain of three
@@ -488,6 +529,8 @@ def main():
         extras["while_loop_8192x10"] = bench_while()
         log("FFT pipelined with its inverse: 512 x 65536 complex fp32")
         extras["fft_pipeline_512x65536"] = bench_fft()
+        log("saxpy: 5e7 fp32 elements, one stage and a two-stage MapReduce with an fp32 sum")
+        extras["saxpy_5e7"] = bench_saxpy()
         log("Segmentation: 60 MiB gray volume, one stage and a 3-stage chain")
         extras["segment_60MiB"] = bench_segment()
         out["extras"] = extras
