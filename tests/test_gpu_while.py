@@ -136,3 +136,20 @@ def test_while_rejections():
         p.run([img, img, h, s, c])                                          # in place is rejected
     assert e.value.status == sk.EINVAL
     p.destroy()
+
+
+def test_bench_size_8192_config2_body():
+    """The bench workload's body and size (config-2 chain on 8192^2, limit 10),
+    with a threshold that stops the loop after the third iteration, checked in
+    full against the oracle's loop."""
+    img = synth.image(synth.SEED_PIPE_FUSED, 8192, 8192)
+    st = BODIES["cfg2"]
+    s = [int(x[0]) for x in _sums(img, st, "hist_sum", 3)]
+    if s[2] < min(s[0], s[1]):
+        cmp, thr = ">=", s[2] + 1
+    elif s[2] > max(s[0], s[1]):
+        cmp, thr = "<=", s[2] - 1
+    else:                                   # not separable at 3: run to a limit of 3
+        cmp, thr = ">=", 0
+    n = _check(img, st, "hist_sum", 0, cmp, thr, 10 if thr else 3)
+    assert n == 3
