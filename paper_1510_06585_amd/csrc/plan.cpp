@@ -199,6 +199,8 @@ int expected_nargs(const Linear& L) {
 }
 
 static bool dense_ok(const skel_buffer& b, int64_t esize) {
+    for (int d = 0; d < b.ndim; ++d)
+        if (b.shape[d] == 0) return true;   // no elements: any strides describe the same (empty) buffer
     int64_t stride = esize;
     for (int d = b.ndim - 1; d >= 0; --d) {
         if (b.stride_bytes[d] != 0 && b.stride_bytes[d] != stride && b.shape[d] > 1) return false;

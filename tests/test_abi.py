@@ -215,3 +215,12 @@ def test_fft_chain_structure_and_limits():
     with pytest.raises(sk.SkelError) as e:
         sk.Plan(sk.image_chain(st + [("saxpy", {"a": 1.0})]), args)
     assert e.value.status == sk.ETYPE
+
+
+def test_empty_buffers_with_any_strides_compile():
+    # zero-element tensors get strides that are not row-major products (e.g.
+    # (3, 0, 2) -> (2, 2, 1)); with no elements any strides are accepted
+    b = sk.proto([3, 0, 2], sk.U8)
+    b.stride_bytes[0], b.stride_bytes[1], b.stride_bytes[2] = 2, 2, 1
+    d = sk.Plan(sk.image_chain([("segment", {})]), [b, b]).describe()
+    assert d["kernels"][0]["grid"] == 0

@@ -96,3 +96,13 @@ def test_bench_size_512_transforms_sampled():
         err = np.linalg.norm(got[pick] - ref, axis=-1) / np.linalg.norm(ref, axis=-1)
         assert err.max() <= 2e-5, (opt, err.max())
         assert len(d["kernels"]) == (3 if opt is None else 4)
+
+
+def test_empty_batch_runs_nothing():
+    x = torch.zeros(0, N, 2, device="cuda")
+    y = torch.zeros(0, N, 2, device="cuda")
+    p = sk.Plan(sk.image_chain([("fft", {}), ("ifft", {})]), [x, y])
+    p.run([x, y])
+    torch.cuda.synchronize()
+    assert y.shape == (0, N, 2)
+    p.destroy()

@@ -105,3 +105,14 @@ def test_tuners_cover_gray_chains(tmp_path):
     torch.cuda.synchronize()
     assert np.array_equal(out.cpu().numpy(), oracle.run_segment_chain(vol, [(0, 0), (100, 200), (5, 9)]))
     p.destroy()
+
+
+def test_empty_volume_runs_nothing():
+    for shape in [(0,), (0, 5, 7), (3, 0, 2)]:
+        vol = torch.zeros(shape, dtype=torch.uint8, device="cuda")
+        out = torch.zeros(shape, dtype=torch.uint8, device="cuda")
+        p = sk.Plan(sk.image_chain([("segment", {}), ("segment", {"lo": 3, "hi": 9})]), [vol, out])
+        p.run([vol, out])
+        torch.cuda.synchronize()
+        assert p.describe()["kernels"][0]["grid"] == 0
+        p.destroy()
