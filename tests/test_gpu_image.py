@@ -35,6 +35,20 @@ def test_config2_pipeline_mapreduce_8192(options):
     assert int(h.sum()) == 4 * 8192 * 8192 and (h[:, 128:] == 0).all()
 
 
+def test_config2_chain_near_the_2gib_limit():
+    """22000 x 22000 RGBA (1.94 GB per image, just under the 2^31-byte image
+    limit): byte offsets near the top of the 32-bit buffer range, fused chain
+    against the full oracle."""
+    H = W = 22000
+    assert H * W * 4 < (1 << 31)
+    img = synth.image(synth.SEED_PIPE_FUSED + 7, H, W)
+    out, h, s = run_image(CFG2, img, "hist_sum", {})
+    ref, rh, rs = oracle.run_image_pipeline(img, CFG2, "hist_sum")
+    assert_image_equal(out, ref, "config2 22000^2")
+    assert (h == rh).all() and (s == rs).all()
+    del out, ref, img
+
+
 # Image sizes the paper's Table 5 lists (W x H), plus ragged and tiny shapes.
 SIZES = [(4288, 2848), (1800, 1125), (1440, 900), (256, 512), (512, 512), (2048, 2048),
          (1, 1), (3, 5), (5, 3), (257, 9), (300, 7), (251, 40), (252, 33), (253, 31), (508, 17), (4, 1000), (1023, 1)]
