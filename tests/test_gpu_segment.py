@@ -116,3 +116,14 @@ def test_empty_volume_runs_nothing():
         torch.cuda.synchronize()
         assert p.describe()["kernels"][0]["grid"] == 0
         p.destroy()
+
+
+def test_volume_near_the_2gib_limit():
+    """2047 x 1023 x 1023 voxels (2.14 GB, just under the 2^31-voxel limit,
+    and not a multiple of 16: the ragged tail at the top of the 32-bit range),
+    a two-stage chain checked on every voxel."""
+    shape = (2047, 1023, 1023)
+    n = shape[0] * shape[1] * shape[2]
+    assert n < (1 << 31) and n % 16
+    vol = synth.gray_volume(synth.SEED_SEGMENT + 9, *shape)
+    _check(vol, [(0, 0), (100, 200)])

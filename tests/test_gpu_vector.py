@@ -111,3 +111,10 @@ def test_inplace_and_aliasing():
     with pytest.raises(sk.SkelError) as e:
         p.run(args)
     assert e.value.status == sk.EINVAL
+
+
+def test_saxpy_near_the_2gib_limit():
+    """(2^31 - 64) / 4 - 3 fp32 elements: byte offsets near the top of the
+    2^31-byte vector limit, ragged against the 4-element vectors."""
+    n = ((1 << 31) - 64) // 4 - 3
+    check([("saxpy", {"a": 1.5})], n, 17, {}, reduce=None)
