@@ -155,3 +155,20 @@ def test_cost_train_and_select_on_synthetic_law(tmp_path):
     assert len(everything) == n_valid
     with pytest.raises(sk.SkelError):
         sk.cost_rank(comp_root, proto, w, 0)
+
+
+def test_trained_model_beats_the_plan_without_it(tmp_path):
+    """A scaled-down selector experiment (250 training compositions x 16
+    sampled configurations, 24 held-out compositions timed exhaustively): the
+    network trained on the GPU picks plans with a lower mean regret than the
+    default plan (the method without it), the untrained network and a random
+    configuration."""
+    from paper_1510_06585_amd import selector
+    r = selector.experiment(n_train=250, n_test=24, per_train=16, seed=7, epochs=200, workdir=str(tmp_path),
+                            log=lambda *a: None)
+    reg = r["regret"]
+    print({k: v["mean"] for k, v in reg.items()})
+    assert reg["model"]["mean"] < reg["default"]["mean"]
+    assert reg["model"]["mean"] < reg["untrained"]["mean"]
+    assert reg["model"]["mean"] < reg["random"]["mean"]
+    assert reg["model_top3_timed"]["mean"] <= reg["model"]["mean"] + 1e-9
