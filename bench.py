@@ -10,7 +10,7 @@ oracle's throughput on the host, the fused-vs-plain speedup and, under
 requests, while Loop, FFT pipeline, Segmentation).
 
   python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-extras]
-                  [--no-cpu-baseline] [--selector] [--profile-run] [--config1-only]
+                  [--no-cpu-baseline] [--selector] [--profile-run] [--filter-pipeline-only]
 """
 from __future__ import annotations
 
@@ -28,8 +28,8 @@ HBM_PEAK_GBS = 8000.0                                   # MI355X HBM3E, GB/s
 VALU_LANE_OPS = 256 * 64 * 2.4e9                        # 256 CUs x 64 lanes x 2.4 GHz
 NBODY_LANE_OPS_PER_PAIR = 13                            # 13 VALU issues per pair, v_rsq_f32 included
 METRIC = "Gelem/s & % HBM roofline per skeleton; fused/learned vs plain speedup"
-CFG2 = [("noise", {"seed": 0x1510}), ("solarise", {}), ("blur5", {}), ("mirror", {})]
-CFG1 = [("noise", {"seed": 0x1510}), ("solarise", {}), ("mirror", {})]
+PIPE_NSBM = [("noise", {"seed": 0x1510}), ("solarise", {}), ("blur5", {}), ("mirror", {})]
+PIPE_NSM = [("noise", {"seed": 0x1510}), ("solarise", {}), ("mirror", {})]
 
 
 def log(*a):
@@ -147,13 +147,13 @@ def cpu_baseline(img, budget_s=12.0):
     reps, t = 0, 0.0
     while reps < 2 or t < budget_s:
         t0 = time.perf_counter()
-        oracle.run_image_pipeline(img, CFG2, "hist_sum")
+        oracle.run_image_pipeline(img, PIPE_NSBM, "hist_sum")
         t += time.perf_counter() - t0
         reps += 1
     px = img.shape[0] * img.shape[1]
     oracle.set_threads(1)
     t0 = time.perf_counter()
-    oracle.run_image_pipeline(img, CFG2, "hist_sum")
+    oracle.run_image_pipeline(img, PIPE_NSBM, "hist_sum")
     t1 = time.perf_counter() - t0
     oracle.set_threads(cores)
     return {"value": round(px * reps / t / 1e9, 6), "unit": "Gelem/s", "cores": cores, "kind": "oracle",
@@ -174,7 +174,7 @@ def image_args(img, reduce="hist_sum"):
     return a
 
 
-def bench_config2(steps, warmup, do_cpu):
+def bench_fused_mapreduce_8192(steps, warmup, do_cpu):
     import torch
     import paper_1510_06585_amd as sk
     import synth
@@ -182,7 +182,7 @@ def bench_config2(steps, warmup, do_cpu):
     img = synth.image(synth.SEED_PIPE_FUSED, H, W)
     args = image_args(img)
     bound = sk.bind(args)
-    root = sk.image_chain(CFG2, "hist_sum")
+    root = sk.image_chain(PIPE_NSBM, "hist_sum")
     fused = sk.Plan(root, args)
     plain = sk.Plan(root, args, {"fusion": sk.FUSE_OFF})
     wall, ev_ms = timed_runs(lambda: fused.run(bound), steps, warmup)
@@ -233,13 +233,13 @@ def bench_config2(steps, warmup, do_cpu):
     return out, img
 
 
-def bench_config1():
+def bench_filter_pipeline_1024():
     import paper_1510_06585_amd as sk
     import synth
     img = synth.image(synth.SEED_PIPE_PLAIN, 1024, 1024)
     args = image_args(img, None)
     b = sk.bind(args)
-    root = sk.image_chain(CFG1)
+    root = sk.image_chain(PIPE_NSM)
     res = {}
     for name, opt in (("plain", {"fusion": sk.FUSE_OFF}), ("fused", {})):
         p = sk.Plan(root, args, opt)
@@ -287,7 +287,7 @@ def bench_batch():
         reqs.append(image_args(synth.image(4000 + r, s, s)))
     px = sum(s * s for s in sides)
     algo = sum(2.0 * s * s * 4 + 4128 for s in sides)
-    root = sk.image_chain(CFG2, "hist_sum")
+    root = sk.image_chain(PIPE_NSBM, "hist_sum")
     proto = [sk.proto([8, 8, 4], sk.U8)] * 2 + [sk.proto([4, 256], sk.U32), sk.proto([4], sk.U64)]
     res = {"requests": 256, "pixels": px}
     bp = sk.Plan(root, proto)
@@ -318,7 +318,7 @@ def bench_batch():
 def bench_while():
     """While Loop with the device-evaluated condition vs the paper's host-side
     evaluation (run the body, read its sums back, test on the host) on the
-    config-2 body over 8192^2, 10 iterations."""
+    noise>solarise>blur>mirror MapReduce body over 8192^2, 10 iterations."""
     import numpy as np
     import torch
     import paper_1510_06585_amd as sk
@@ -331,7 +331,7 @@ def bench_while():
     hist = torch.zeros(4, 256, dtype=torch.int32, device="cuda")
     sums = torch.zeros(4, dtype=torch.int64, device="cuda")
     count = torch.zeros(1, dtype=torch.int32, device="cuda")
-    body = sk.image_chain(CFG2, "hist_sum")
+    body = sk.image_chain(PIPE_NSBM, "hist_sum")
     res = {"iterations": iters}
     wplan = sk.Plan(sk.LoopWhile(body, iters, 0, ">=", 0), [x, y, hist, sums, count])
     wb = sk.bind([x, y, hist, sums, count])
@@ -459,14 +459,14 @@ def bench_segment():
 
 
 def profile_run(steps):
-    """Short run for hardware-counter passes: the fused config-2 kernel and a
+    """Short run for hardware-counter passes: the fused 8192^2 Pipeline+MapReduce kernel and a
     plain copy of the same image (the byte-count reference), `steps` each."""
     import torch
     import paper_1510_06585_amd as sk
     import synth
     img = synth.image(synth.SEED_PIPE_FUSED, 8192, 8192)
     args = image_args(img)
-    fused = sk.Plan(sk.image_chain(CFG2, "hist_sum"), args)
+    fused = sk.Plan(sk.image_chain(PIPE_NSBM, "hist_sum"), args)
     copy = sk.Plan(sk.Loop(sk.Map("mirror"), 2), args[:2])   # two mirrors = identity: one copy kernel
     for _ in range(steps):
         fused.run(args)
@@ -487,7 +487,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--selector", action="store_true", help="run the learned-selector experiment instead")
     ap.add_argument("--profile-run", action="store_true", help="short run for rocprofv3 counter passes")
-    ap.add_argument("--config1-only", action="store_true",
+    ap.add_argument("--filter-pipeline-only", action="store_true",
                     help="only the 1024x1024 filter pipeline, plain and fused (for a per-stage kernel trace)")
     ap.add_argument("--selector-dir", default=None, help="where the selector experiment keeps its databases")
     ap.add_argument("--selector-train", type=int, default=1000)
@@ -507,8 +507,8 @@ def main():
     if a.profile_run:
         profile_run(a.steps)
         return
-    if a.config1_only:
-        print(json.dumps(bench_config1()), flush=True)
+    if a.filter_pipeline_only:
+        print(json.dumps(bench_filter_pipeline_1024()), flush=True)
         return
     if a.selector:
         from paper_1510_06585_amd import selector
@@ -516,11 +516,11 @@ def main():
                                              workdir=a.selector_dir, log=log)), flush=True)
         return
     log("config 2: fused pipeline + mapreduce 8192x8192")
-    out, img = bench_config2(a.steps, a.warmup, not a.no_cpu_baseline)
+    out, img = bench_fused_mapreduce_8192(a.steps, a.warmup, not a.no_cpu_baseline)
     if not a.no_extras:
         extras = {}
         log("config 1: filter pipeline 1024x1024 plain vs fused")
-        extras["filter_pipeline_1024"] = bench_config1()
+        extras["filter_pipeline_1024"] = bench_filter_pipeline_1024()
         log("config 3: n-body 65536 x 20 iterations")
         extras["nbody_65536_x20"] = bench_nbody()
         log("config 4: 256 batched uneven requests")

@@ -4,7 +4,7 @@ into the short text summaries kept under ``profiles/``.
 The counter passes are taken one counter group per run (rocprofv3 does not
 split counters over passes), from the repository root with TMPDIR=/tmp:
 
-  rocprofv3 --kernel-trace --stats -d DIR -o cfg2 --output-format csv -- python3 bench.py --no-extras --no-cpu-baseline
+  rocprofv3 --kernel-trace --stats -d DIR -o fused8192 --output-format csv -- python3 bench.py --no-extras --no-cpu-baseline
   rocprofv3 --kernel-trace --stats -d DIR -o all --output-format csv -- python3 bench.py --no-cpu-baseline
   rocprofv3 --pmc FETCH_SIZE -d DIR -o fetch --output-format csv -- python3 bench.py --profile-run --steps 5
   rocprofv3 --pmc WRITE_SIZE -d DIR -o write --output-format csv -- python3 bench.py --profile-run --steps 5
@@ -17,7 +17,7 @@ the same image; FETCH_SIZE / WRITE_SIZE (KiB per dispatch) of the fused kernel
 are scaled by (known bytes / counter reading) of the copy kernel, which
 corrects for the share of the memory channels the counters observe.
 
-  python -m paper_1510_06585_amd.rocprof_harness --trace DIR/cfg2_kernel_stats.csv \
+  python -m paper_1510_06585_amd.rocprof_harness --trace DIR/fused8192_kernel_stats.csv \
       --trace-all DIR/all_kernel_stats.csv --fetch DIR/fetch_counter_collection.csv \
       --write DIR/write_counter_collection.csv --sq DIR/sq_counter_collection.csv --out profiles/
 """
@@ -36,7 +36,7 @@ FUSED_NAME = "img_noise_sol_blur_reduce"
 COPY = "img_band_kernel<0, 0, false, false, 0>"
 COPY_BYTES = 2 * 8192 * 8192 * 4
 COMMANDS = (
-    "rocprofv3 --kernel-trace --stats -d DIR -o cfg2 --output-format csv -- python3 bench.py --no-extras "
+    "rocprofv3 --kernel-trace --stats -d DIR -o fused8192 --output-format csv -- python3 bench.py --no-extras "
     "--no-cpu-baseline",
     "rocprofv3 --kernel-trace --stats -d DIR -o all --output-format csv -- python3 bench.py --no-cpu-baseline",
     "rocprofv3 --pmc FETCH_SIZE -d DIR -o fetch --output-format csv -- python3 bench.py --profile-run --steps 5",
@@ -44,7 +44,7 @@ COMMANDS = (
     "rocprofv3 --pmc SQ_WAVES SQ_INSTS_VALU SQ_INSTS_LDS SQ_LDS_BANK_CONFLICT SQ_ACTIVE_INST_VALU "
     "SQ_ACTIVE_INST_LDS SQ_BUSY_CYCLES SQ_WAVE_CYCLES -d DIR -o sq --output-format csv -- "
     "python3 bench.py --profile-run --steps 3",
-    "python -m paper_1510_06585_amd.rocprof_harness --trace DIR/cfg2_kernel_stats.csv "
+    "python -m paper_1510_06585_amd.rocprof_harness --trace DIR/fused8192_kernel_stats.csv "
     "--trace-all DIR/all_kernel_stats.csv --fetch DIR/fetch_counter_collection.csv "
     "--write DIR/write_counter_collection.csv --sq DIR/sq_counter_collection.csv --out profiles/",
 )
@@ -85,8 +85,8 @@ def traffic(fetch_csv, write_csv):
             "bytes_per_launch": kf * 1024.0 * sf + kw * 1024.0 * sw}
 
 
-COMMAND_CONFIG1 = ("rocprofv3 --kernel-trace --stats -d DIR -o cfg1 --output-format csv -- python3 bench.py "
-                   "--config1-only")
+COMMAND_FILTER_PIPELINE = ("rocprofv3 --kernel-trace --stats -d DIR -o filter1024 --output-format csv -- python3 bench.py "
+                   "--filter-pipeline-only")
 COMMAND_MLP = ("rocprofv3 --pmc SQ_INSTS_VALU_MFMA_MOPS_F32 SQ_VALU_MFMA_BUSY_CYCLES SQ_INSTS_VALU SQ_BUSY_CYCLES "
                "-d DIR -o mfma --output-format csv -- python3 -m paper_1510_06585_amd.mlp_probe")
 HBM_PEAK_GBS = 8000.0
@@ -102,7 +102,7 @@ def row_work():
     batch_bytes = sum(2 * s * s * 4 + 4128 for s in sides)
     fft_bytes = 2 * 512 * 65536 * 8
     return [
-        ("img_batch_kernel<9, 0, true, true, 2>", "256 uneven requests, config-2 chain", "hbm", batch_bytes),
+        ("img_batch_kernel<9, 0, true, true, 2>", "256 uneven requests, noise>solarise>blur>mirror + histogram", "hbm", batch_bytes),
         ("fft_pass_kernel<0>", "pass A, 512 x 65536 complex fp32", "hbm", fft_bytes),
         ("fft_pass_kernel<1>", "fused pass B+A, 512 x 65536 complex fp32", "hbm", fft_bytes),
         ("fft_pass_kernel<2>", "pass B, 512 x 65536 complex fp32", "hbm", fft_bytes),
@@ -138,20 +138,20 @@ def main():
     ap.add_argument("--write")
     ap.add_argument("--sq")
     ap.add_argument("--trace-all", help="kernel stats of the whole bench run (every skeleton)")
-    ap.add_argument("--trace-config1", help="kernel stats of the config-1 run alone (per-stage times)")
+    ap.add_argument("--trace-filter-pipeline", help="kernel stats of the 1024x1024 filter-pipeline run alone (per-stage times)")
     ap.add_argument("--mlp-counters", help="MFMA counter pass over the cost-model MLP kernels")
     ap.add_argument("--out", required=True)
     a = ap.parse_args()
     os.makedirs(a.out, exist_ok=True)
-    if a.trace_config1:
+    if a.trace_filter_pipeline:
         c1 = ["# rocprofv3 summary: filter pipeline 1024x1024 RGBA u8 (noise > solarise > mirror), plain plan "
               "(one kernel per stage) and fused plan, 220 runs each", "",
-              "Command (repository root on the GPU box, TMPDIR=/tmp):", "", "```", COMMAND_CONFIG1, "```", "",
+              "Command (repository root on the MI355X host, TMPDIR=/tmp):", "", "```", COMMAND_FILTER_PIPELINE, "```", "",
               "Kernels: `img_band_kernel<1, 0, false, false, 0>` is the noise stage, `<2, 0, false, false, 0>` "
               "solarise, `<0, 0, false, false, 2>` mirror (a copy with the store flipped), "
               "`<9, 0, false, false, 2>` the fused chain.", "",
               "| kernel | calls | avg us | min us | max us |", "|---|---|---|---|---|"]
-        for r in kernel_stats(a.trace_config1):
+        for r in kernel_stats(a.trace_filter_pipeline):
             c1.append(f"| `{r['name'][:90]}` | {r['calls']} | {r['avg_ns']/1e3:.2f} | {r['min_ns']/1e3:.2f} | "
                       f"{r['max_ns']/1e3:.2f} |")
         open(os.path.join(a.out, "img_filter_pipeline_1024.md"), "w").write("\n".join(c1) + "\n")
@@ -160,7 +160,7 @@ def main():
         n = 16384
         fwd_flops = 2 * n * (24 * 64 + 64 * 64 + 64)
         ml = ["# rocprofv3 counters: cost-model MLP kernels on the matrix cores (16384 samples, 24->64->64->1)", "",
-              "Command (repository root on the GPU box, TMPDIR=/tmp):", "", "```", COMMAND_MLP, "```", "",
+              "Command (repository root on the MI355X host, TMPDIR=/tmp):", "", "```", COMMAND_MLP, "```", "",
               "The script runs `skel_mlp_forward` and `skel_mlp_grad` three times each on 16384 random "
               f"samples.  The forward pass's layer products are {fwd_flops} flops; one "
               "SQ_INSTS_VALU_MFMA_MOPS_F32 count is 512 flops.", "",
@@ -185,9 +185,9 @@ def main():
            "bytes_per_launch": round(tr["bytes_per_launch"]),
            "algorithmic_bytes": 2 * 8192 * 8192 * 4 + 4128, **{k: round(v, 4) for k, v in tr.items()}}
     json.dump(rec, open(os.path.join(a.out, f"traffic_{FUSED_NAME}.json"), "w"), indent=1)
-    lines = ["# rocprofv3 summary: fused Pipeline+MapReduce, 8192x8192 RGBA u8 (config-2 bench run: fused "
+    lines = ["# rocprofv3 summary: fused Pipeline+MapReduce, 8192x8192 RGBA u8 (the bench run of this workload: fused "
              "plan, plain plan, copy reference)",
-             "", "Commands (repository root on the GPU box, TMPDIR=/tmp):", "", "```"] + list(COMMANDS)
+             "", "Commands (repository root on the MI355X host, TMPDIR=/tmp):", "", "```"] + list(COMMANDS)
     lines += ["```", "", "## Kernel trace (--kernel-trace --stats)", "",
               "| kernel | calls | avg us | min us | max us |", "|---|---|---|---|---|"]
     for r in st:
@@ -205,7 +205,7 @@ def main():
     open(os.path.join(a.out, f"{FUSED_NAME}_8192.md"), "w").write("\n".join(lines) + "\n")
     if a.trace_all:
         al = ["# rocprofv3 kernel trace of the whole bench run (every skeleton's kernels)", "",
-              "Command (repository root on the GPU box, TMPDIR=/tmp):", "", "```", COMMANDS[1], "```", "",
+              "Command (repository root on the MI355X host, TMPDIR=/tmp):", "", "```", COMMANDS[1], "```", "",
               "Averages mix workloads where one kernel serves several (e.g. the fused image kernel runs the "
               "8192^2 image and, in the sequential baseline of the batch, 256 smaller ones).", "",
               "| kernel | calls | avg us | min us | max us |", "|---|---|---|---|---|"]

@@ -46,11 +46,11 @@ def hist_args(H, W):
     return img(H, W) + [sk.proto([4, 256], sk.U32), sk.proto([4], sk.U64)]
 
 
-CFG2 = [("noise", {"seed": 0x1510}), ("solarise", {}), ("blur5", {}), ("mirror", {})]
+PIPE_NSBM = [("noise", {"seed": 0x1510}), ("solarise", {}), ("blur5", {}), ("mirror", {})]
 
 
-def test_fused_config2_is_one_kernel_with_mirror_on_the_store():
-    p = sk.Plan(sk.image_chain(CFG2, "hist_sum"), hist_args(64, 100))
+def test_fused_nsbm_chain_is_one_kernel_with_mirror_on_the_store():
+    p = sk.Plan(sk.image_chain(PIPE_NSBM, "hist_sum"), hist_args(64, 100))
     d = p.describe()
     assert d["stages"] == ["noise", "solarise", "blur5", "mirror"]
     assert len(d["kernels"]) == 1
@@ -77,7 +77,7 @@ def test_fusion_splits_at_second_stencil():
 
 
 def test_split_mask_partitions_and_rejects_two_stencils():
-    root = sk.image_chain(CFG2, "hist_sum")
+    root = sk.image_chain(PIPE_NSBM, "hist_sum")
     d = sk.Plan(root, hist_args(8, 8), {"fusion": sk.FUSE_MASK, "split_mask": 0b0010}).describe()
     assert [k["stages"] for k in d["kernels"]] == [[0, 2], [2, 4]]
     d = sk.Plan(root, hist_args(8, 8), {"fusion": sk.FUSE_MASK, "split_mask": 0b1000}).describe()
@@ -89,7 +89,7 @@ def test_split_mask_partitions_and_rejects_two_stencils():
 
 
 def test_generic_variant_selected_on_request():
-    root = sk.image_chain(CFG2, "hist_sum")
+    root = sk.image_chain(PIPE_NSBM, "hist_sum")
     d = sk.Plan(root, hist_args(8, 8), {"variant": 1}).describe()
     assert d["kernels"][0]["name"] == "img_generic_blur_reduce"
 
@@ -99,13 +99,13 @@ def test_type_and_shape_errors():
         sk.Plan(sk.Pipeline(sk.Map("noise"), sk.Map("saxpy", a=1.0)), img(4, 4))
     assert e.value.status == sk.ETYPE
     with pytest.raises(sk.SkelError) as e:
-        sk.Plan(sk.image_chain(CFG2, "hist_sum"), img(4, 4))          # missing reduce outputs
+        sk.Plan(sk.image_chain(PIPE_NSBM, "hist_sum"), img(4, 4))          # missing reduce outputs
     assert e.value.status == sk.EINVAL
     with pytest.raises(sk.SkelError) as e:
-        sk.Plan(sk.image_chain(CFG2), [sk.proto([4, 4, 4], sk.U8), sk.proto([4, 5, 4], sk.U8)])
+        sk.Plan(sk.image_chain(PIPE_NSBM), [sk.proto([4, 4, 4], sk.U8), sk.proto([4, 5, 4], sk.U8)])
     assert e.value.status == sk.ESHAPE
     with pytest.raises(sk.SkelError) as e:
-        sk.Plan(sk.image_chain(CFG2), img(2, 65537))
+        sk.Plan(sk.image_chain(PIPE_NSBM), img(2, 65537))
     assert e.value.status == sk.EUNSUPPORTED
     with pytest.raises(sk.SkelError) as e:
         sk.Plan(sk.MapReduce(sk.Map("saxpy", a=1.0), sk.RED_HIST256_SUM),
@@ -119,7 +119,7 @@ def test_type_and_shape_errors():
         sk.Map(99)
     assert e.value.status == sk.EINVAL
     with pytest.raises(sk.SkelError):
-        sk.Plan(sk.image_chain(CFG2), img(8, 8), {"wg": 96})
+        sk.Plan(sk.image_chain(PIPE_NSBM), img(8, 8), {"wg": 96})
 
 
 def test_nbody_structure_checks():
@@ -153,7 +153,7 @@ def test_mirror_only_chain_takes_domain_from_arguments():
 
 
 def test_features_reflect_configuration():
-    root = sk.image_chain(CFG2, "hist_sum")
+    root = sk.image_chain(PIPE_NSBM, "hist_sum")
     f_on = sk.features(root, hist_args(1024, 1024))
     f_off = sk.features(root, hist_args(1024, 1024), {"fusion": sk.FUSE_OFF})
     assert f_on.shape == (24,)

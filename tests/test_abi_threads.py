@@ -6,7 +6,7 @@ import threading
 
 import paper_1510_06585_amd as sk
 
-CFG2 = [("noise", {"seed": 0x1510}), ("solarise", {}), ("blur5", {}), ("mirror", {})]
+PIPE_NSBM = [("noise", {"seed": 0x1510}), ("solarise", {}), ("blur5", {}), ("mirror", {})]
 
 
 def _protos(H, W):
@@ -14,18 +14,18 @@ def _protos(H, W):
 
 
 def test_concurrent_plan_compilation_and_thread_local_errors():
-    ref = sk.Plan(sk.image_chain(CFG2, "hist_sum"), _protos(777, 1234)).describe()
+    ref = sk.Plan(sk.image_chain(PIPE_NSBM, "hist_sum"), _protos(777, 1234)).describe()
     errors = []
 
     def work(tid):
         try:
             for i in range(40):
-                d = sk.Plan(sk.image_chain(CFG2, "hist_sum"), _protos(777, 1234)).describe()
+                d = sk.Plan(sk.image_chain(PIPE_NSBM, "hist_sum"), _protos(777, 1234)).describe()
                 assert d["kernels"] == ref["kernels"], "different plan"
                 # a failing compile: its message names this thread's bad shape
                 bad = [sk.proto([5 + tid, 7, 4], sk.U8), sk.proto([6 + tid, 7, 4], sk.U8)]
                 try:
-                    sk.Plan(sk.image_chain(CFG2), bad)
+                    sk.Plan(sk.image_chain(PIPE_NSBM), bad)
                     raise AssertionError("mismatched shapes accepted")
                 except sk.SkelError as e:
                     assert e.status == sk.ESHAPE

@@ -12,7 +12,7 @@ from gpu_helpers import assert_image_equal, cuda
 
 pytestmark = pytest.mark.gpu
 
-CFG2 = [("noise", {"seed": synth.NOISE_SEED}), ("solarise", {}), ("blur5", {}), ("mirror", {})]
+PIPE_NSBM = [("noise", {"seed": synth.NOISE_SEED}), ("solarise", {}), ("blur5", {}), ("mirror", {})]
 
 
 def make_reqs(sides, seed0, reduce="hist_sum"):
@@ -43,14 +43,14 @@ def test_small_uneven_batch_against_oracle():
     bound = sk.bind_batch(reqs)
     # one, two and four wavefronts per work-group take groups of consecutive tiles
     for opt in ({"tile_h": 16}, {"tile_h": 5, "wg": 64}, {"tile_h": 7, "wg": 128}):
-        p = plan_for(CFG2, options=opt)
+        p = plan_for(PIPE_NSBM, options=opt)
         for rep in range(2):   # capture, then replay of the same request set (pre-marshalled)
             for a in reqs:
                 a[1].fill_(7)
             p.batch_run(reqs if rep == 0 else bound)
             torch.cuda.synchronize()
             for (H, W), img, a in zip(sides, imgs, reqs):
-                ref, rh, rs = oracle.run_image_pipeline(img, CFG2, "hist_sum")
+                ref, rh, rs = oracle.run_image_pipeline(img, PIPE_NSBM, "hist_sum")
                 assert_image_equal(a[1].cpu().numpy(), ref, f"{H}x{W} {opt} rep{rep}")
                 assert (a[2].cpu().numpy().view(np.uint32) == rh).all()
                 assert (a[3].cpu().numpy().view(np.uint64) == rs).all()
@@ -67,10 +67,10 @@ def test_pointwise_batch_without_reduce():
         assert_image_equal(a[1].cpu().numpy(), oracle.run_image_pipeline(img, st), "pointwise batch")
 
 
-def test_config4_256_requests_match_single_runs_and_oracle_sample():
+def test_256_uneven_requests_match_single_runs_and_oracle_sample():
     sides = synth.batch_sides(synth.SEED_BATCH, 256)
     reqs, imgs = make_reqs([(s, s) for s in sides], 4000)
-    p = plan_for(CFG2, options={"tile_h": 64})
+    p = plan_for(PIPE_NSBM, options={"tile_h": 64})
     p.batch_run(reqs)
     torch.cuda.synchronize()
     order = np.argsort(sides)
@@ -83,12 +83,12 @@ def test_config4_256_requests_match_single_runs_and_oracle_sample():
         assert int(h.sum()) == 4 * s * s and (h[:, 128:] == 0).all()
         assert all(int(sm[c]) == int((np.arange(256) * h[c].astype(np.int64)).sum()) for c in range(4))
         if r in sample:
-            ref, rh, rs = oracle.run_image_pipeline(imgs[r], CFG2, "hist_sum")
+            ref, rh, rs = oracle.run_image_pipeline(imgs[r], PIPE_NSBM, "hist_sum")
             assert_image_equal(a[1].cpu().numpy(), ref, f"request {r} side {s}")
             assert (h == rh).all() and (sm == rs).all()
         else:
             single = [a[0], torch.empty_like(a[0]), torch.empty_like(a[2]), torch.empty_like(a[3])]
-            q = sk.Plan(sk.image_chain(CFG2, "hist_sum"), single)
+            q = sk.Plan(sk.image_chain(PIPE_NSBM, "hist_sum"), single)
             q.run(single)
             torch.cuda.synchronize()
             assert torch.equal(single[1], a[1]) and torch.equal(single[2], a[2]) and torch.equal(single[3], a[3])
@@ -96,7 +96,7 @@ def test_config4_256_requests_match_single_runs_and_oracle_sample():
 
 
 def test_batch_needs_a_fused_plan():
-    p = plan_for(CFG2, options={"fusion": sk.FUSE_OFF})
+    p = plan_for(PIPE_NSBM, options={"fusion": sk.FUSE_OFF})
     reqs, _ = make_reqs([(4, 4)], 1)
     with pytest.raises(sk.SkelError) as e:
         p.batch_run(reqs)

@@ -12,39 +12,39 @@ from gpu_helpers import assert_image_equal, run_image
 
 pytestmark = pytest.mark.gpu
 
-CFG1 = [("noise", {"seed": synth.NOISE_SEED}), ("solarise", {}), ("mirror", {})]
-CFG2 = [("noise", {"seed": synth.NOISE_SEED}), ("solarise", {}), ("blur5", {}), ("mirror", {})]
+PIPE_NSM = [("noise", {"seed": synth.NOISE_SEED}), ("solarise", {}), ("mirror", {})]
+PIPE_NSBM = [("noise", {"seed": synth.NOISE_SEED}), ("solarise", {}), ("blur5", {}), ("mirror", {})]
 
 
 @pytest.mark.parametrize("options", [{"fusion": sk.FUSE_OFF}, {}, {"variant": 1}],
                          ids=["plain", "fused", "interpreter"])
-def test_config1_filter_pipeline_1024(options):
+def test_filter_pipeline_1024(options):
     img = synth.image(synth.SEED_PIPE_PLAIN, 1024, 1024)
-    ref = oracle.run_image_pipeline(img, CFG1)
-    out, _, _ = run_image(CFG1, img, None, options)
-    assert_image_equal(out, ref, "config1")
+    ref = oracle.run_image_pipeline(img, PIPE_NSM)
+    out, _, _ = run_image(PIPE_NSM, img, None, options)
+    assert_image_equal(out, ref, "filter pipeline 1024")
 
 
 @pytest.mark.parametrize("options", [{}, {"fusion": sk.FUSE_OFF}], ids=["fused", "plain"])
-def test_config2_pipeline_mapreduce_8192(options):
+def test_pipeline_mapreduce_8192(options):
     img = synth.image(synth.SEED_PIPE_FUSED, 8192, 8192)
-    ref, rh, rs = oracle.run_image_pipeline(img, CFG2, "hist_sum")
-    out, h, s = run_image(CFG2, img, "hist_sum", options)
-    assert_image_equal(out, ref, "config2")
+    ref, rh, rs = oracle.run_image_pipeline(img, PIPE_NSBM, "hist_sum")
+    out, h, s = run_image(PIPE_NSBM, img, "hist_sum", options)
+    assert_image_equal(out, ref, "pipeline+mapreduce 8192")
     assert (h == rh).all() and (s == rs).all()
     assert int(h.sum()) == 4 * 8192 * 8192 and (h[:, 128:] == 0).all()
 
 
-def test_config2_chain_near_the_2gib_limit():
+def test_pipeline_mapreduce_near_the_2gib_limit():
     """22000 x 22000 RGBA (1.94 GB per image, just under the 2^31-byte image
     limit): byte offsets near the top of the 32-bit buffer range, fused chain
     against the full oracle."""
     H = W = 22000
     assert H * W * 4 < (1 << 31)
     img = synth.image(synth.SEED_PIPE_FUSED + 7, H, W)
-    out, h, s = run_image(CFG2, img, "hist_sum", {})
-    ref, rh, rs = oracle.run_image_pipeline(img, CFG2, "hist_sum")
-    assert_image_equal(out, ref, "config2 22000^2")
+    out, h, s = run_image(PIPE_NSBM, img, "hist_sum", {})
+    ref, rh, rs = oracle.run_image_pipeline(img, PIPE_NSBM, "hist_sum")
+    assert_image_equal(out, ref, "pipeline+mapreduce 22000^2")
     assert (h == rh).all() and (s == rs).all()
     del out, ref, img
 
@@ -55,12 +55,12 @@ SIZES = [(4288, 2848), (1800, 1125), (1440, 900), (256, 512), (512, 512), (2048,
 
 
 @pytest.mark.parametrize("W,H", SIZES, ids=[f"{w}x{h}" for w, h in SIZES])
-def test_config2_chain_odd_sizes(W, H):
+def test_pipeline_mapreduce_odd_sizes(W, H):
     img = synth.image(W * 7 + H, H, W)
-    ref, rh, rs = oracle.run_image_pipeline(img, CFG2, "hist_sum")
+    ref, rh, rs = oracle.run_image_pipeline(img, PIPE_NSBM, "hist_sum")
     for opt in ({}, {"fusion": sk.FUSE_OFF}, {"variant": 1}, {"wg": 64, "tile_h": 7},
                 {"wg": 128, "tile_h": 1}):
-        out, h, s = run_image(CFG2, img, "hist_sum", opt)
+        out, h, s = run_image(PIPE_NSBM, img, "hist_sum", opt)
         assert_image_equal(out, ref, f"{W}x{H} {opt}")
         assert (h == rh).all() and (s == rs).all(), opt
 
@@ -132,26 +132,26 @@ def test_inplace_pointwise_and_rejections():
     out, _, _ = run_image(st, img, None, {}, inplace=True)
     assert_image_equal(out, oracle.run_image_pipeline(img, st), "inplace")
     with pytest.raises(sk.SkelError) as e:
-        run_image(CFG1, img, None, {}, inplace=True)
+        run_image(PIPE_NSM, img, None, {}, inplace=True)
     assert e.value.status == sk.EINVAL
     # unfused: the mirror kernel reads a scratch image, so in-place is legal
-    out, _, _ = run_image(CFG1, img, None, {"fusion": sk.FUSE_OFF}, inplace=True)
-    assert_image_equal(out, oracle.run_image_pipeline(img, CFG1), "inplace unfused")
+    out, _, _ = run_image(PIPE_NSM, img, None, {"fusion": sk.FUSE_OFF}, inplace=True)
+    assert_image_equal(out, oracle.run_image_pipeline(img, PIPE_NSM), "inplace unfused")
 
 
 def test_empty_images_and_reduce_outputs_overwritten():
     for H, W in ((0, 5), (5, 0)):
         img = np.zeros((H, W, 4), np.uint8)
-        out, h, s = run_image(CFG2, img, "hist_sum")
+        out, h, s = run_image(PIPE_NSBM, img, "hist_sum")
         assert (h == 0).all() and (s == 0).all()
     img = synth.image(11, 50, 50)
     from gpu_helpers import image_args, image_results
     args = image_args(img, "hist_sum")
-    p = sk.Plan(sk.image_chain(CFG2, "hist_sum"), args)
+    p = sk.Plan(sk.image_chain(PIPE_NSBM, "hist_sum"), args)
     p.run(args)
     p.run(args)        # a second run overwrites, it does not accumulate
     out, h, s = image_results(args, "hist_sum")
-    ref, rh, rs = oracle.run_image_pipeline(img, CFG2, "hist_sum")
+    ref, rh, rs = oracle.run_image_pipeline(img, PIPE_NSBM, "hist_sum")
     assert (h == rh).all() and (s == rs).all()
 
 
@@ -164,13 +164,13 @@ def test_reduce_rerun_overwrites_with_many_merge_chunks(options):
     from gpu_helpers import image_args, image_results
     H, W = 1500, 2048
     args = image_args(synth.image(21, H, W), "hist_sum")
-    p = sk.Plan(sk.image_chain(CFG2, "hist_sum"), args, options)
+    p = sk.Plan(sk.image_chain(PIPE_NSBM, "hist_sum"), args, options)
     for r in range(3):
         img = synth.image(21 + r, H, W)
         args[0].copy_(torch.from_numpy(img).cuda())
         p.run(args)
         out, h, s = image_results(args, "hist_sum")
-        ref, rh, rs = oracle.run_image_pipeline(img, CFG2, "hist_sum")
+        ref, rh, rs = oracle.run_image_pipeline(img, PIPE_NSBM, "hist_sum")
         assert_image_equal(out, ref, f"run {r}")
         assert (h == rh).all() and (s == rs).all(), f"run {r}"
     p.destroy()
@@ -178,9 +178,9 @@ def test_reduce_rerun_overwrites_with_many_merge_chunks(options):
 
 def test_sum_only_reduce():
     img = synth.image(12, 77, 301)
-    ref, _, rs = oracle.run_image_pipeline(img, CFG2, "sum")
+    ref, _, rs = oracle.run_image_pipeline(img, PIPE_NSBM, "sum")
     for opt in ({}, {"fusion": sk.FUSE_OFF}):
-        out, _, s = run_image(CFG2, img, "sum", opt)
+        out, _, s = run_image(PIPE_NSBM, img, "sum", opt)
         assert_image_equal(out, ref, "sum")
         assert (s == rs).all()
 
@@ -189,7 +189,7 @@ def test_wrong_shapes_rejected_at_run():
     img = synth.image(13, 16, 16)
     from gpu_helpers import image_args
     args = image_args(img)
-    p = sk.Plan(sk.image_chain(CFG1), args)
+    p = sk.Plan(sk.image_chain(PIPE_NSM), args)
     bad = image_args(synth.image(13, 16, 17))
     with pytest.raises(sk.SkelError) as e:
         p.run(bad)

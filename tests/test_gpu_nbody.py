@@ -48,7 +48,7 @@ def test_small_systems_against_fp64(N):
         assert (p[:, 3] == pos[:, 3]).all()     # masses carried unchanged
 
 
-def test_config3_65536_bodies_20_steps():
+def test_nbody_65536_bodies_20_steps():
     pos, vel = synth.nbody(synth.SEED_NBODY, 65536)
     p, v = run_gpu(pos, vel, 20)
     ref, _ = oracle.nbody_run(pos, vel, 20, G=G, eps=EPS, dt=DT)

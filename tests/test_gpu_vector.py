@@ -59,7 +59,7 @@ def test_saxpy_single_stage_map_and_reversal_only():
     check([("mirror", {}), ("mirror", {})], 10001, 7, {}, reduce="sum")
 
 
-def test_config5_sized_chain_2p26():
+def test_saxpy_chain_2p26():
     rng = np.random.default_rng(synth.SEED_SELECT)
     st = [("saxpy", {"a": synth.saxpy_coeff(rng)}), ("mirror", {}), ("saxpy", {"a": synth.saxpy_coeff(rng)})]
     check(st, 1 << 26, 8, {})

@@ -16,7 +16,7 @@ pytestmark = pytest.mark.gpu
 
 BODIES = {
     "blur": [("blur5", {})],
-    "cfg2": [("noise", {"seed": synth.NOISE_SEED}), ("solarise", {}), ("blur5", {}), ("mirror", {})],
+    "nsbm": [("noise", {"seed": synth.NOISE_SEED}), ("solarise", {}), ("blur5", {}), ("mirror", {})],
     "noise_mirror": [("noise", {"seed": 5}), ("mirror", {})],
 }
 
@@ -85,7 +85,7 @@ def test_while_stops_where_the_oracle_stops(body, shape):
                          ids=["fused", "plain", "interpreter", "small-tiles"])
 def test_while_configurations_and_parities(options):
     img = synth.image(31, 257, 333)
-    stages = BODIES["cfg2"]
+    stages = BODIES["nsbm"]
     for limit in (1, 2, 3, 4, 9):
         _check(img, stages, "hist_sum", 2, ">=", 0, limit, every=2, options=options)
     _check(img, stages, "sum", 3, ">=", 0, 4, options=options)
@@ -138,12 +138,12 @@ def test_while_rejections():
     p.destroy()
 
 
-def test_bench_size_8192_config2_body():
-    """The bench workload's body and size (config-2 chain on 8192^2, limit 10),
+def test_bench_size_8192_nsbm_body():
+    """The bench workload's body and size (noise>solarise>blur>mirror MapReduce on 8192^2, limit 10),
     with a threshold that stops the loop after the third iteration, checked in
     full against the oracle's loop."""
     img = synth.image(synth.SEED_PIPE_FUSED, 8192, 8192)
-    st = BODIES["cfg2"]
+    st = BODIES["nsbm"]
     s = [int(x[0]) for x in _sums(img, st, "hist_sum", 3)]
     if s[2] < min(s[0], s[1]):
         cmp, thr = ">=", s[2] + 1
