@@ -3,7 +3,7 @@
 The paper builds a profile per (computation, workload) pair by search
 (Algorithm 1) and derives configurations for new pairs by interpolating over
 stored profiles (Sec. 3.2; Euclidean nearest neighbour above three
-dimensions).  This driver measures how well the GPU-trained MLP picks a fused
+dimensions).  This module measures how well the GPU-trained MLP picks a fused
 plan and tile configuration for compositions it has never seen:
 
 1. draw random skeleton compositions (2-6 stages over noise, solarise, mirror,
