@@ -52,3 +52,19 @@ def test_round_trip_and_parseval():
     assert np.allclose((np.abs(X) ** 2).sum(-1), 65536 * (np.abs(z) ** 2).sum(-1), rtol=1e-12)
     back = oracle.fft_chain(x, ["fft", "ifft"])
     assert np.abs(back - z).max() < 1e-12
+
+
+def test_full_length_bins_against_direct_sums():
+    # at the real transform length, a few output bins of the forward and
+    # inverse stages written out as the defining sums (fp64, O(N) per bin)
+    N = 65536
+    rng = np.random.default_rng(1234)
+    x = (rng.uniform(-1, 1, N) + 1j * rng.uniform(-1, 1, N)).astype(np.complex64).astype(np.complex128)
+    X = oracle.fft_chain(_pack(x[None]), ["fft"])[0]
+    Y = oracle.fft_chain(_pack(x[None]), ["ifft"])[0]
+    n = np.arange(N)
+    for k in (0, 1, 255, 256, 4097, 32768, 65535):
+        fwd = np.sum(x * np.exp(-2j * np.pi * ((n * k) % N) / N))
+        inv = np.sum(x * np.exp(2j * np.pi * ((n * k) % N) / N)) / N
+        assert abs(X[k] - fwd) <= 1e-9 * max(1.0, abs(fwd)), (k, X[k], fwd)
+        assert abs(Y[k] - inv) <= 1e-12 * max(1.0, abs(inv)) + 1e-13, (k, Y[k], inv)
