@@ -145,8 +145,10 @@ typedef struct skel_loop_state {
  * continues while  sum[channel] <cmp> threshold  holds for the uint64
  * channel sums of the body's reduce output, and fewer than the state's
  * `iterations` iterations have run.  The condition is evaluated on the device;
- * the host reads a one-word flag every check_every iterations (0 = 8) to
- * decide whether to enqueue more. */
+ * the host enqueues blocks of check_every iterations (0 = 8) and, after
+ * enqueuing a block, reads the one-word flag left by the block before it to
+ * decide whether to enqueue more (a block enqueued after the condition failed
+ * does no work). */
 enum { SKEL_CMP_GT = 0, SKEL_CMP_GE = 1, SKEL_CMP_LT = 2, SKEL_CMP_LE = 3 };
 typedef struct skel_loop_cond {
     int32_t channel;      /* 0..3 */
@@ -233,7 +235,8 @@ skel_status skel_loop(skel_node body, const skel_loop_state* st, skel_node* out)
  * and writes out = x, hist/sum of the last iteration and count.  Plan
  * arguments: in u8 [H,W,4], out u8 [H,W,4], [hist u32 [4,256],] sum u64 [4],
  * count u32 [1]; in and out must not overlap.  Unlike other runs, a run of a
- * while plan synchronises `stream` every cond->check_every iterations. */
+ * while plan blocks the host: after enqueuing each block of
+ * cond->check_every iterations it waits for the previous block to finish. */
 skel_status skel_loop_while(skel_node body, const skel_loop_state* st, const skel_loop_cond* cond,
                             skel_node* out);
 

@@ -180,9 +180,13 @@ skel_status run_image(skel_plan p, const skel_buffer* args, hipStream_t s) {
 // even, the plan's second image otherwise, so a loop that runs to its limit
 // ends in out; every kernel of an iteration is guarded by the device flag,
 // which the step kernel clears when the condition fails or the limit is
-// reached.  The host enqueues check_every iterations, then reads the flag
-// (one 4-byte copy and a stream synchronisation) to decide whether to enqueue
-// more; a final guarded copy moves a result that ended in the second image.
+// reached.  The host enqueues blocks of check_every iterations; after each
+// block it enqueues a 4-byte copy of the flag into a pinned slot and records
+// an event, then waits for the previous block's event and reads that block's
+// flag.  The GPU thus always has the newest block queued while the host
+// waits, and a block enqueued after the condition failed runs only guarded
+// no-op kernels.  A final guarded copy moves a result that ended in the
+// second image.
 skel_status run_image_while(skel_plan p, const skel_buffer* args, hipStream_t s) {
     const Linear& L = p->lin;
     const int nargs = (int)p->proto.size();
@@ -198,7 +202,7 @@ skel_status run_image_while(skel_plan p, const skel_buffer* args, hipStream_t s)
     const int every = L.wcond.check_every > 0 ? L.wcond.check_every : 8;
     HIP_TRY(launch_while_init(p->wstate, s));
     int it = 0;
-    while (it < L.while_max) {
+    for (int block = 0; it < L.while_max; ++block) {
         for (int j = 0; j < every && it < L.while_max; ++j, ++it) {
             auto dst_of = [&](int i) { return (L.while_max - 1 - i) % 2 == 0 ? args[1].data : p->wbuf; };
             void* src = it == 0 ? args[0].data : dst_of(it - 1);
@@ -232,10 +236,12 @@ skel_status run_image_while(skel_plan p, const skel_buffer* args, hipStream_t s)
             }
             HIP_TRY(launch_while_step(p->wstate, sum, wc, count, s));
         }
-        if (it < L.while_max) {
-            HIP_TRY(hipMemcpyAsync(p->h_flag, p->wstate, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
-            HIP_TRY(hipStreamSynchronize(s));
-            if (*p->h_flag == 0) break;
+        if (it >= L.while_max) break;
+        HIP_TRY(hipMemcpyAsync(p->h_flag + block % 2, p->wstate, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipEventRecord(p->wev[block % 2], s));
+        if (block > 0) {
+            HIP_TRY(hipEventSynchronize(p->wev[(block - 1) % 2]));
+            if (p->h_flag[(block - 1) % 2] == 0) break;
         }
     }
     HIP_TRY(launch_while_copy(p->wstate, p->wbuf, args[1].data, (uint64_t)p->sh.W * p->sh.H * 4,
@@ -411,6 +417,7 @@ skel_status ensure_resources(skel_plan p) {
         HIP_TRY(hipMalloc(&p->wbuf, std::max<size_t>(bytes, 16)));
         HIP_TRY(hipMalloc(&p->wstate, 256));
         HIP_TRY(hipHostMalloc((void**)&p->h_flag, 256, hipHostMallocDefault));
+        for (hipEvent_t& e : p->wev) HIP_TRY(hipEventCreateWithFlags(&e, hipEventDisableTiming));
     }
     if (p->lin.dom == DOM_NBODY && p->cfg.fusion == SKEL_FUSE_OFF && !p->nb_acc)
         HIP_TRY(hipMalloc(&p->nb_acc, sizeof(float4) * std::max<int64_t>(p->sh.N, 1)));
@@ -658,6 +665,8 @@ skel_status skel_plan_destroy(skel_plan p) {
     if (p->wbuf) hipFree(p->wbuf);
     if (p->wstate) hipFree(p->wstate);
     if (p->h_flag) hipHostFree(p->h_flag);
+    for (hipEvent_t e : p->wev)
+        if (e) hipEventDestroy(e);
     if (p->d_segs) hipFree(p->d_segs);
     if (p->h_segs) hipHostFree(p->h_segs);
     if (p->b_rows) hipFree(p->b_rows);

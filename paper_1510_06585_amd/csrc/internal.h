@@ -130,7 +130,8 @@ struct skel_plan_s {
     uint32_t* hrows = nullptr;      // image reduce: histogram rows, one per work-group
     void* wbuf = nullptr;           // while Loop: second image of the iteration ping-pong
     uint32_t* wstate = nullptr;     // while Loop: device {continue flag, iterations run}
-    uint32_t* h_flag = nullptr;     // while Loop: pinned host copy of the flag
+    uint32_t* h_flag = nullptr;     // while Loop: pinned host copies of the flag, one per block in flight
+    hipEvent_t wev[2] = {nullptr, nullptr};  // while Loop: completion of those copies
     float4* nb_acc = nullptr;
     // N-body loop graph
     hipStream_t cap_stream = nullptr;

@@ -91,12 +91,15 @@ def test_while_configurations_and_parities(options):
     _check(img, stages, "sum", 3, ">=", 0, 4, options=options)
 
 
-def test_while_plan_reruns_and_checks_every_iteration():
+@pytest.mark.parametrize("every", [1, 2, 5])
+def test_while_plan_reruns_and_checks_every_iteration(every):
+    # the stop falls inside a later block of `every` iterations, with the block
+    # after it already enqueued when the host reads the flag
     img = synth.image(40, 128, 260)
     stages = BODIES["blur"]
     seq = _sums(img, stages, "hist_sum", 12)
     thr = int(seq[6][0])
-    p, args, out, h, s, n = _run(img, stages, "hist_sum", 0, ">", thr, 12, every=1)
+    p, args, out, h, s, n = _run(img, stages, "hist_sum", 0, ">", thr, 12, every=every)
     ref, rh, rs, rn = oracle.run_image_while(img, stages, "hist_sum", 0, ">", thr, 12)
     assert n == rn and (out == ref).all() and (s == rs).all()
     img2 = synth.image(41, 128, 260)          # a second run on the same plan with new data
