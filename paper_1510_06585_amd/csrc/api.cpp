@@ -362,12 +362,12 @@ skel_status run_nbody(skel_plan p, const skel_buffer* args, hipStream_t s) {
         hipGraph_t g = nullptr;
         hipError_t e = hipStreamEndCapture(p->cap_stream, &g);
         if (st) {
-            if (g) hipGraphDestroy(g);
+            if (g) (void)hipGraphDestroy(g);
             return st;
         }
         if (e != hipSuccess) return set_error(SKEL_EDEVICE, "graph capture failed: %s", hipGetErrorString(e));
         e = hipGraphInstantiate(&p->gexec, g, nullptr, nullptr, 0);
-        hipGraphDestroy(g);
+        (void)hipGraphDestroy(g);
         if (e != hipSuccess) return set_error(SKEL_EDEVICE, "graph instantiate failed: %s", hipGetErrorString(e));
         p->gkey = key;
     }
@@ -561,7 +561,14 @@ skel_status skel_plan_compile(skel_node root, const skel_buffer* proto, int32_t 
     for (auto& b : p->proto) b.data = nullptr;
     node_addref(root);
     p->root = root;
-    hipGetDevice(&p->device);
+    // Compiling needs no device (describe() and the structure queries work
+    // without one); with none, device 0 is recorded and the first run reports
+    // the device error.  The failed query's error state is cleared so that it
+    // is not taken for a later launch's.
+    if (hipGetDevice(&p->device) != hipSuccess) {
+        p->device = 0;
+        (void)hipGetLastError();
+    }
     *out = p;
     return SKEL_OK;
 }
@@ -658,26 +665,26 @@ skel_status skel_plan_destroy(skel_plan p) {
     clear_error();
     if (!p) return SKEL_OK;
     for (void* q : p->scratch)
-        if (q) hipFree(q);
-    if (p->partials) hipFree(p->partials);
-    if (p->fft_tw) hipFree(p->fft_tw);
-    if (p->hrows) hipFree(p->hrows);
-    if (p->wbuf) hipFree(p->wbuf);
-    if (p->wstate) hipFree(p->wstate);
-    if (p->h_flag) hipHostFree(p->h_flag);
+        if (q) (void)hipFree(q);
+    if (p->partials) (void)hipFree(p->partials);
+    if (p->fft_tw) (void)hipFree(p->fft_tw);
+    if (p->hrows) (void)hipFree(p->hrows);
+    if (p->wbuf) (void)hipFree(p->wbuf);
+    if (p->wstate) (void)hipFree(p->wstate);
+    if (p->h_flag) (void)hipHostFree(p->h_flag);
     for (hipEvent_t e : p->wev)
-        if (e) hipEventDestroy(e);
-    if (p->d_segs) hipFree(p->d_segs);
-    if (p->h_segs) hipHostFree(p->h_segs);
-    if (p->b_rows) hipFree(p->b_rows);
-    if (p->d_tile_req) hipFree(p->d_tile_req);
-    if (p->nb_acc) hipFree(p->nb_acc);
-    if (p->gexec) hipGraphExecDestroy(p->gexec);
-    if (p->bexec) hipGraphExecDestroy(p->bexec);
-    if (p->cap_stream) hipStreamDestroy(p->cap_stream);
-    if (p->d_reqs) hipFree(p->d_reqs);
-    if (p->d_counter) hipFree(p->d_counter);
-    if (p->h_reqs) hipHostFree(p->h_reqs);
+        if (e) (void)hipEventDestroy(e);
+    if (p->d_segs) (void)hipFree(p->d_segs);
+    if (p->h_segs) (void)hipHostFree(p->h_segs);
+    if (p->b_rows) (void)hipFree(p->b_rows);
+    if (p->d_tile_req) (void)hipFree(p->d_tile_req);
+    if (p->nb_acc) (void)hipFree(p->nb_acc);
+    if (p->gexec) (void)hipGraphExecDestroy(p->gexec);
+    if (p->bexec) (void)hipGraphExecDestroy(p->bexec);
+    if (p->cap_stream) (void)hipStreamDestroy(p->cap_stream);
+    if (p->d_reqs) (void)hipFree(p->d_reqs);
+    if (p->d_counter) (void)hipFree(p->d_counter);
+    if (p->h_reqs) (void)hipHostFree(p->h_reqs);
     node_release(p->root);
     delete p;
     return SKEL_OK;

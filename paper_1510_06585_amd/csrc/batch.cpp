@@ -119,10 +119,10 @@ extern "C" skel_status skel_batch_run(skel_plan p, const skel_buffer* args, int3
     // the histogram rows: wait for them before anything is rewritten.
     HIP_TRY(hipStreamSynchronize(s));
     if ((size_t)nreq > p->d_reqs_cap) {
-        if (p->d_reqs) hipFree(p->d_reqs);
-        if (p->h_reqs) hipHostFree(p->h_reqs);
-        if (p->d_segs) hipFree(p->d_segs);
-        if (p->h_segs) hipHostFree(p->h_segs);
+        if (p->d_reqs) (void)hipFree(p->d_reqs);
+        if (p->h_reqs) (void)hipHostFree(p->h_reqs);
+        if (p->d_segs) (void)hipFree(p->d_segs);
+        if (p->h_segs) (void)hipHostFree(p->h_segs);
         p->d_reqs = nullptr;
         p->h_reqs = nullptr;
         p->d_segs = nullptr;
@@ -171,7 +171,7 @@ extern "C" skel_status skel_batch_run(skel_plan p, const skel_buffer* args, int3
     const size_t words = 4 * (size_t)K.bins;
     const size_t rows = (size_t)(tiles / gw);
     if (red >= 0 && rows * words > p->b_rows_cap) {
-        if (p->b_rows) hipFree(p->b_rows);
+        if (p->b_rows) (void)hipFree(p->b_rows);
         p->b_rows = nullptr;
         p->b_rows_cap = 0;
         HIP_TRY(hipMalloc(&p->b_rows, sizeof(uint32_t) * rows * words));
@@ -184,7 +184,7 @@ extern "C" skel_status skel_batch_run(skel_plan p, const skel_buffer* args, int3
         for (int64_t t = p->h_reqs[k].tile_begin; t < end; ++t) tile_req[(size_t)t] = (uint16_t)k;
     }
     if ((size_t)tiles > p->tile_req_cap) {
-        if (p->d_tile_req) hipFree(p->d_tile_req);
+        if (p->d_tile_req) (void)hipFree(p->d_tile_req);
         p->d_tile_req = nullptr;
         p->tile_req_cap = 0;
         HIP_TRY(hipMalloc(&p->d_tile_req, sizeof(uint16_t) * tiles));
@@ -222,7 +222,7 @@ extern "C" skel_status skel_batch_run(skel_plan p, const skel_buffer* args, int3
     p->batch_grid = grid;
 
     if (p->bexec) {
-        hipGraphExecDestroy(p->bexec);
+        (void)hipGraphExecDestroy(p->bexec);
         p->bexec = nullptr;
     }
     if (!p->cap_stream) HIP_TRY(hipStreamCreateWithFlags(&p->cap_stream, hipStreamNonBlocking));
@@ -242,12 +242,12 @@ extern "C" skel_status skel_batch_run(skel_plan p, const skel_buffer* args, int3
     hipGraph_t g = nullptr;
     hipError_t e4 = hipStreamEndCapture(p->cap_stream, &g);
     if (e1 || e2 || e3 || e4) {
-        if (g) hipGraphDestroy(g);
+        if (g) (void)hipGraphDestroy(g);
         return set_error(SKEL_EDEVICE, "batch graph capture failed: %s",
                          hipGetErrorString(e1 ? e1 : (e2 ? e2 : (e3 ? e3 : e4))));
     }
     hipError_t e = hipGraphInstantiate(&p->bexec, g, nullptr, nullptr, 0);
-    hipGraphDestroy(g);
+    (void)hipGraphDestroy(g);
     if (e != hipSuccess) return set_error(SKEL_EDEVICE, "batch graph instantiate failed: %s", hipGetErrorString(e));
     p->bkey = key;
     HIP_TRY(hipGraphLaunch(p->bexec, s));

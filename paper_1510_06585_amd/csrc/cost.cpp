@@ -109,8 +109,9 @@ extern "C" skel_status skel_mlp_grad(const float* params, const float* X, const 
     float* work = nullptr;
     HIP_TRY(hipMallocAsync((void**)&work, sizeof(float) * mlp_grad_work_floats(n), s));
     hipError_t e = launch_mlp_grad(params, X, t, n, grad, loss, work, s);
-    hipFreeAsync(work, s);
-    if (e != hipSuccess) return set_error(SKEL_EDEVICE, "MLP gradient launch: %s", hipGetErrorString(e));
+    const hipError_t ef = hipFreeAsync(work, s);
+    if (e == hipSuccess) e = ef;
+    if (e != hipSuccess) return set_error(SKEL_EDEVICE, "MLP gradient: %s", hipGetErrorString(e));
     return SKEL_OK;
 }
 
@@ -172,8 +173,8 @@ extern "C" skel_status skel_cost_train(const char* db_path, const char* weights_
     auto cleanup = [&]() {
         for (void* q : {(void*)dX, (void*)dT, (void*)dP, (void*)dG, (void*)dM, (void*)dV, (void*)dW, (void*)dL,
                         (void*)dY, (void*)dI})
-            if (q) hipFree(q);
-        if (hI) hipHostFree(hI);
+            if (q) (void)hipFree(q);
+        if (hI) (void)hipHostFree(hI);
     };
     hipError_t e = hipSuccess;
     auto A = [&](hipError_t r) {
@@ -221,7 +222,7 @@ extern "C" skel_status skel_cost_train(const char* db_path, const char* weights_
     A(hipStreamSynchronize(s));
     A(hipMemcpy(Y.data(), dY, sizeof(float) * n, hipMemcpyDeviceToHost));
     A(hipMemcpy(m.theta.data(), dP, sizeof(float) * kNP, hipMemcpyDeviceToHost));
-    hipStreamDestroy(s);
+    (void)hipStreamDestroy(s);
     cleanup();
     if (e != hipSuccess) return set_error(SKEL_EDEVICE, "training: %s", hipGetErrorString(e));
     double L = 0;
@@ -264,7 +265,7 @@ skel_status predict_all(skel_node root, const skel_buffer* proto, int32_t nargs,
     Y.assign(n, 0.0f);
     if (!e) e = hipMemcpy(Y.data(), dY, sizeof(float) * n, hipMemcpyDeviceToHost);
     for (void* q : {(void*)dP, (void*)dX, (void*)dY})
-        if (q) hipFree(q);
+        if (q) (void)hipFree(q);
     if (e != hipSuccess) return set_error(SKEL_EDEVICE, "cost model inference: %s", hipGetErrorString(e));
     return SKEL_OK;
 }

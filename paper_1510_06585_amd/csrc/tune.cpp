@@ -233,10 +233,10 @@ struct Timer {
         HIP_TRY(hipEventCreate(&e1));
         return SKEL_OK;
     }
-    ~Timer() {
-        if (e0) hipEventDestroy(e0);
-        if (e1) hipEventDestroy(e1);
-        if (s) hipStreamDestroy(s);
+    ~Timer() {   // teardown: errors are not reportable here
+        if (e0) (void)hipEventDestroy(e0);
+        if (e1) (void)hipEventDestroy(e1);
+        if (s) (void)hipStreamDestroy(s);
     }
     skel_status time(skel_node root, const skel_buffer* args, int32_t nargs, const Config& c, int reps,
                      double* med, double* mn) {
@@ -247,18 +247,24 @@ struct Timer {
         if (st) return SKEL_EINVAL;
         for (int w = 0; w < 3 && !st; ++w) st = skel_plan_run(p, args, nargs, s);
         times.clear();
-        for (int r = 0; r < reps && !st; ++r) {
-            hipEventRecord(e0, s);
+        hipError_t e = hipSuccess;
+        for (int r = 0; r < reps && !st && e == hipSuccess; ++r) {
+            e = hipEventRecord(e0, s);
+            if (e != hipSuccess) break;
             st = skel_plan_run(p, args, nargs, s);
-            hipEventRecord(e1, s);
-            hipEventSynchronize(e1);
+            if (st) break;
             float ms = 0;
-            hipEventElapsedTime(&ms, e0, e1);
-            times.push_back(ms * 1000.0f);
+            e = hipEventRecord(e1, s);
+            if (e == hipSuccess) e = hipEventSynchronize(e1);
+            if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+            if (e == hipSuccess) times.push_back(ms * 1000.0f);
         }
-        hipStreamSynchronize(s);
+        const hipError_t es = hipStreamSynchronize(s);
+        if (e == hipSuccess) e = es;
         skel_plan_destroy(p);
-        if (st) return st == SKEL_EINVAL ? SKEL_EDEVICE : st;
+        if (st) return st == SKEL_EINVAL ? SKEL_EDEVICE : st;   // a compiled plan that fails to run is a device error
+        if (e != hipSuccess) return set_error(SKEL_EDEVICE, "timing a candidate: %s", hipGetErrorString(e));
+        if (times.empty()) return set_error(SKEL_EINVAL, "no timed repetitions");
         std::sort(times.begin(), times.end());
         *med = times[times.size() / 2];
         *mn = times.front();
