@@ -11,6 +11,7 @@ requests, while Loop, FFT pipeline, Segmentation).
 
   python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-extras]
                   [--no-cpu-baseline] [--selector] [--profile-run] [--filter-pipeline-only]
+                  [--while-only]
 """
 from __future__ import annotations
 
@@ -489,6 +490,9 @@ def main():
     ap.add_argument("--profile-run", action="store_true", help="short run for rocprofv3 counter passes")
     ap.add_argument("--filter-pipeline-only", action="store_true",
                     help="only the 1024x1024 filter pipeline, plain and fused (for a per-stage kernel trace)")
+    ap.add_argument("--while-only", action="store_true",
+                    help="only the 8192x8192 x 10 while Loop against its host-checked and unchecked forms "
+                         "(for a kernel trace)")
     ap.add_argument("--selector-dir", default=None, help="where the selector experiment keeps its databases")
     ap.add_argument("--selector-train", type=int, default=1000)
     ap.add_argument("--selector-test", type=int, default=200)
@@ -509,6 +513,9 @@ def main():
         return
     if a.filter_pipeline_only:
         print(json.dumps(bench_filter_pipeline_1024()), flush=True)
+        return
+    if a.while_only:
+        print(json.dumps(bench_while()), flush=True)
         return
     if a.selector:
         from paper_1510_06585_amd import selector

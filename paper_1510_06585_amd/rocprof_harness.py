@@ -20,6 +20,10 @@ corrects for the share of the memory channels the counters observe.
   python -m paper_1510_06585_amd.rocprof_harness --trace DIR/fused8192_kernel_stats.csv \
       --trace-all DIR/all_kernel_stats.csv --fetch DIR/fetch_counter_collection.csv \
       --write DIR/write_counter_collection.csv --sq DIR/sq_counter_collection.csv --out profiles/
+
+The while Loop's trace (``bench.py --while-only`` under the trace command in
+COMMAND_WHILE, its stdout kept in a file) is summarised with
+``--trace-while DIR/while8192_kernel_stats.csv --while-json FILE``.
 """
 from __future__ import annotations
 
@@ -87,6 +91,8 @@ def traffic(fetch_csv, write_csv):
 
 COMMAND_FILTER_PIPELINE = ("rocprofv3 --kernel-trace --stats -d DIR -o filter1024 --output-format csv -- python3 bench.py "
                    "--filter-pipeline-only")
+COMMAND_WHILE = ("rocprofv3 --kernel-trace --stats -d DIR -o while8192 --output-format csv -- python3 bench.py "
+                 "--while-only")
 COMMAND_MLP = ("rocprofv3 --pmc SQ_INSTS_VALU_MFMA_MOPS_F32 SQ_VALU_MFMA_BUSY_CYCLES SQ_INSTS_VALU SQ_BUSY_CYCLES "
                "-d DIR -o mfma --output-format csv -- python3 -m paper_1510_06585_amd.mlp_probe")
 HBM_PEAK_GBS = 8000.0
@@ -140,6 +146,8 @@ def main():
     ap.add_argument("--trace-all", help="kernel stats of the whole bench run (every skeleton)")
     ap.add_argument("--trace-filter-pipeline", help="kernel stats of the 1024x1024 filter-pipeline run alone (per-stage times)")
     ap.add_argument("--mlp-counters", help="MFMA counter pass over the cost-model MLP kernels")
+    ap.add_argument("--trace-while", help="kernel stats of the 8192x8192 x 10 while Loop run alone")
+    ap.add_argument("--while-json", help="the JSON line the traced while run printed (per-iteration wall times)")
     ap.add_argument("--out", required=True)
     a = ap.parse_args()
     os.makedirs(a.out, exist_ok=True)
@@ -155,6 +163,34 @@ def main():
             c1.append(f"| `{r['name'][:90]}` | {r['calls']} | {r['avg_ns']/1e3:.2f} | {r['min_ns']/1e3:.2f} | "
                       f"{r['max_ns']/1e3:.2f} |")
         open(os.path.join(a.out, "img_filter_pipeline_1024.md"), "w").write("\n".join(c1) + "\n")
+    if a.trace_while:
+        stats = kernel_stats(a.trace_while)
+        cw = ["# rocprofv3 summary: while Loop, noise > solarise > blur > mirror + histogram body over "
+              "8192x8192 RGBA u8, 10 iterations", "",
+              "Command (repository root on the MI355X host, TMPDIR=/tmp):", "", "```", COMMAND_WHILE, "```", "",
+              "The run times the while plan (13 runs: 3 warm-up, 10 timed), the same body with the sums read "
+              "back by the host after every iteration (6 runs) and the body alone, unchecked (6 runs), "
+              "10 iterations each.  Per iteration the while plan launches the image kernel, the histogram "
+              "merge and the one-thread step kernel; per run one init kernel and one final guarded copy.", "",
+              "| kernel | calls | avg us | min us | max us |", "|---|---|---|---|---|"]
+        for r in stats:
+            cw.append(f"| `{r['name'][:90]}` | {r['calls']} | {r['avg_ns']/1e3:.2f} | {r['min_ns']/1e3:.2f} | "
+                      f"{r['max_ns']/1e3:.2f} |")
+        busy = {}
+        for key in ("img_", "hist_merge_kernel", "while_step_kernel"):
+            r = [x for x in stats if key in x["name"]]
+            if r:
+                busy[key] = sum(x["avg_ns"] * x["calls"] for x in r) / max(sum(x["calls"] for x in r), 1) / 1e3
+        if busy:
+            cw += ["", "Kernel time per iteration (averages above): " +
+                   ", ".join(f"{k.strip('_')} {v:.2f} us" for k, v in busy.items()) +
+                   f"; total {sum(busy.values()):.2f} us."]
+        if a.while_json:
+            w = json.loads([ln for ln in open(a.while_json) if ln.startswith("{")][-1])
+            cw += ["", "Wall time per iteration under the profiler (ms): "
+                   f"while plan {w['device_condition_ms_per_iteration']}, host-checked body "
+                   f"{w['host_condition_ms_per_iteration']}, unchecked body {w['no_condition_ms_per_iteration']}."]
+        open(os.path.join(a.out, "while_loop_8192.md"), "w").write("\n".join(cw) + "\n")
     if a.mlp_counters:
         cm = counters(a.mlp_counters)
         n = 16384
