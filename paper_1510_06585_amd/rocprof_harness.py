@@ -23,7 +23,8 @@ corrects for the share of the memory channels the counters observe.
 
 The while Loop's trace (``bench.py --while-only`` under the trace command in
 COMMAND_WHILE, its stdout kept in a file) is summarised with
-``--trace-while DIR/while8192_kernel_stats.csv --while-json FILE``.
+``--trace-while DIR/while8192_kernel_stats.csv --while-json FILE
+--while-dispatches DIR/while8192_kernel_trace.csv``.
 """
 from __future__ import annotations
 
@@ -137,6 +138,37 @@ def row_roofline(stats):
     return out
 
 
+def while_phases(path):
+    """Image-kernel durations of the traced while run split by loop form.  The
+    while plan's dispatches end with its last final-copy launch; after it, an
+    iteration whose merge is followed by a device-to-host copy belongs to the
+    host-checked loop, any other to the unchecked one."""
+    import statistics
+    rows = sorted(csv.DictReader(open(path)), key=lambda r: int(r["Start_Timestamp"]))
+    seq = [(r["Kernel_Name"], int(r["Start_Timestamp"]), int(r["End_Timestamp"])) for r in rows]
+    last_copy = max(i for i, x in enumerate(seq) if "while_copy_kernel" in x[0])
+    phase = {"while plan": [], "host-checked": [], "unchecked": []}
+    step = []
+    for i, (name, t0, t1) in enumerate(seq):
+        if "while_step_kernel" in name:
+            step.append(t1 - t0)
+        if "img_" not in name:
+            continue
+        if i < last_copy:
+            phase["while plan"].append(t1 - t0)
+            continue
+        nxt = [x[0] for x in seq[i + 1:i + 4]]
+        phase["host-checked" if any("copyBuffer" in n for n in nxt) else "unchecked"].append(t1 - t0)
+    out = ["", "Image kernel per dispatch, by loop form (from the per-dispatch trace of the same run):", "",
+           "| loop form | dispatches | median us | mean us |", "|---|---|---|---|"]
+    for k, v in phase.items():
+        if v:
+            out.append(f"| {k} | {len(v)} | {statistics.median(v)/1e3:.2f} | {statistics.mean(v)/1e3:.2f} |")
+    if step:
+        out += ["", f"Step kernel: {len(step)} dispatches, median {statistics.median(step)/1e3:.2f} us."]
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--trace")
@@ -148,6 +180,7 @@ def main():
     ap.add_argument("--mlp-counters", help="MFMA counter pass over the cost-model MLP kernels")
     ap.add_argument("--trace-while", help="kernel stats of the 8192x8192 x 10 while Loop run alone")
     ap.add_argument("--while-json", help="the JSON line the traced while run printed (per-iteration wall times)")
+    ap.add_argument("--while-dispatches", help="the per-dispatch kernel trace of the same while run")
     ap.add_argument("--out", required=True)
     a = ap.parse_args()
     os.makedirs(a.out, exist_ok=True)
@@ -182,9 +215,11 @@ def main():
             if r:
                 busy[key] = sum(x["avg_ns"] * x["calls"] for x in r) / max(sum(x["calls"] for x in r), 1) / 1e3
         if busy:
-            cw += ["", "Kernel time per iteration (averages above): " +
+            cw += ["", "Mean per dispatch over all three loop forms: " +
                    ", ".join(f"{k.strip('_')} {v:.2f} us" for k, v in busy.items()) +
                    f"; total {sum(busy.values()):.2f} us."]
+        if a.while_dispatches:
+            cw += while_phases(a.while_dispatches)
         if a.while_json:
             w = json.loads([ln for ln in open(a.while_json) if ln.startswith("{")][-1])
             cw += ["", "Wall time per iteration under the profiler (ms): "
