@@ -1,0 +1,55 @@
+"""CPU tests of the rocprofv3 summary harness's parsers on small synthetic
+trace files: the per-kernel statistics table and the split of the while-Loop
+run's image-kernel dispatches by loop form."""
+import csv
+
+from paper_1510_06585_amd import rocprof_harness as rh
+
+
+def _write(path, header, rows):
+    with open(path, "w", newline="") as f:
+        w = csv.writer(f, quoting=csv.QUOTE_ALL)
+        w.writerow(header)
+        w.writerows(rows)
+
+
+def test_kernel_stats_reads_rocprof_columns(tmp_path):
+    p = tmp_path / "k_kernel_stats.csv"
+    _write(p, ["Name", "Calls", "TotalDurationNs", "AverageNs", "Percentage", "MinNs", "MaxNs", "StdDev"],
+           [["skel::a(int)", "3", "300", "100.0", "75.0", "90", "110", "8.1"],
+            ["skel::b(int)", "1", "100", "100.0", "25.0", "100", "100", "0"]])
+    st = rh.kernel_stats(str(p))
+    assert [r["name"] for r in st] == ["skel::a(int)", "skel::b(int)"]
+    assert st[0]["calls"] == 3 and st[0]["avg_ns"] == 100.0 and st[0]["min_ns"] == 90.0 and st[0]["pct"] == 75.0
+
+
+def test_while_phases_splits_by_loop_form(tmp_path):
+    t = [0]
+
+    def d(name, dur):
+        row = ["KERNEL_DISPATCH", name, str(t[0]), str(t[0] + dur)]
+        t[0] += dur + 10
+        return row
+
+    rows = []
+    for _ in range(2):                      # while plan: 3 iterations per run, then the final copy
+        rows.append(d("skel::while_init_kernel(unsigned int*)", 5))
+        for _ in range(3):
+            rows += [d("void skel::img_band_kernel<9>(skel::ImgGroupArgs)", 1300),
+                     d("skel::hist_merge_kernel(skel::HistFinArgs)", 60),
+                     d("skel::while_step_kernel(unsigned int*)", 48)]
+        rows.append(d("skel::while_copy_kernel(unsigned int const*)", 40))
+    for _ in range(4):                      # host-checked: sums read back after every merge
+        rows += [d("void skel::img_band_kernel<9>(skel::ImgGroupArgs)", 1270),
+                 d("skel::hist_merge_kernel(skel::HistFinArgs)", 60),
+                 d("__amd_rocclr_copyBuffer", 30)]
+    for _ in range(5):                      # unchecked body
+        rows += [d("void skel::img_band_kernel<9>(skel::ImgGroupArgs)", 1250),
+                 d("skel::hist_merge_kernel(skel::HistFinArgs)", 60)]
+    p = tmp_path / "w_kernel_trace.csv"
+    _write(p, ["Kind", "Kernel_Name", "Start_Timestamp", "End_Timestamp"], rows)
+    out = "\n".join(rh.while_phases(str(p)))
+    assert "| while plan | 6 | 1.30 | 1.30 |" in out
+    assert "| host-checked | 4 | 1.27 | 1.27 |" in out
+    assert "| unchecked | 5 | 1.25 | 1.25 |" in out
+    assert "Step kernel: 6 dispatches, median 0.05 us." in out
