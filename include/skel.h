@@ -57,9 +57,11 @@ enum { SKEL_U8 = 0, SKEL_U32 = 1, SKEL_U64 = 2, SKEL_F32 = 3, SKEL_F64 = 4 };
 #define SKEL_IMMUTABLE 1u   /* the skeleton only reads this buffer                   */
 #define SKEL_COPY 2u        /* read whole by every work-group (not partitioned)     */
 
-/* A typed, caller-owned device buffer.  Dense row-major only: stride_bytes
- * may be all zero (meaning dense) or must equal the dense strides; anything
- * else is SKEL_ESHAPE.  ndim is 1..4. */
+/* A typed, caller-owned device buffer.  Dense row-major only: over the
+ * dimensions of extent > 1, stride_bytes are either all zero (meaning dense)
+ * or all equal to the dense strides; anything else, a mix of zero and
+ * non-zero strides included, is SKEL_ESHAPE.  Strides of extent-1 dimensions
+ * and of buffers with no elements are ignored.  ndim is 1..4. */
 typedef struct skel_buffer {
     void* data;
     int32_t dtype;
@@ -289,7 +291,10 @@ skel_status skel_plan_run_event(skel_plan plan, const skel_buffer* args, int32_t
  * with its own H and W (<= 65536).  All requests run in one persistent
  * kernel fed by a work list (largest requests first), captured into a HIP
  * graph that is replayed while the same buffers and shapes are passed again.
- * The plan must be a single-kernel (fully fused) image chain. */
+ * The plan must be a single-kernel (fully fused) image chain.  Within a
+ * request in == out is allowed only for chains without a stencil or mirror;
+ * any other overlap of a written buffer (out, hist, sum) with a buffer of the
+ * same or another request is SKEL_EINVAL (inputs may be shared). */
 skel_status skel_batch_run(skel_plan plan, const skel_buffer* args, int32_t nargs,
                            int32_t nreq, void* stream);
 

@@ -73,14 +73,8 @@ skel_status check_args(skel_plan p, const skel_buffer* args, int32_t nargs) {
         for (int d = 0; d < a.ndim; ++d)
             if (a.shape[d] != q.shape[d])
                 return set_error(SKEL_ESHAPE, "argument %d: shape differs from the compiled plan (recompile for new shapes)", k);
-        int64_t es = (a.dtype == SKEL_U8) ? 1 : ((a.dtype == SKEL_U64 || a.dtype == SKEL_F64) ? 8 : 4), st = es;
-        bool empty = false;
-        for (int d = 0; d < a.ndim; ++d) empty |= a.shape[d] == 0;
-        for (int d = a.ndim - 1; d >= 0 && !empty; --d) {
-            if (a.stride_bytes[d] != 0 && a.stride_bytes[d] != st && a.shape[d] > 1)
-                return set_error(SKEL_ESHAPE, "argument %d: not dense row-major", k);
-            st *= a.shape[d];
-        }
+        const int64_t es = (a.dtype == SKEL_U8) ? 1 : ((a.dtype == SKEL_U64 || a.dtype == SKEL_F64) ? 8 : 4);
+        if (!dense_strides(a, es)) return set_error(SKEL_ESHAPE, "argument %d: not dense row-major", k);
         if (!a.data && range_of(a).hi != range_of(a).lo) return set_error(SKEL_EINVAL, "argument %d: null data", k);
     }
     return SKEL_OK;

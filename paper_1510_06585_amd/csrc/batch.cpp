@@ -27,18 +27,22 @@ using namespace skel;
 
 namespace {
 
+// Byte range [lo, hi) of a dense buffer of esize-byte elements.
+struct Span {
+    uintptr_t lo, hi;
+};
+Span span_of(const skel_buffer& b, int64_t esize) {
+    int64_t n = b.ndim > 0 ? 1 : 0;
+    for (int d = 0; d < b.ndim; ++d) n *= b.shape[d] > 0 ? b.shape[d] : 0;
+    return Span{(uintptr_t)b.data, (uintptr_t)b.data + (uintptr_t)(n * esize)};
+}
+bool spans_overlap(const Span& x, const Span& y) { return x.hi > x.lo && y.hi > y.lo && x.lo < y.hi && y.lo < x.hi; }
+
 skel_status check_req(const skel_buffer* a, int nargs, int red, int r, bool inplace_ok) {
-    for (int k = 0; k < nargs; ++k) {
-        const skel_buffer& b = a[k];
-        for (int d = 0; d < 4; ++d)
-            if (d < b.ndim && b.stride_bytes[d] != 0) {
-                int64_t st = 1;
-                for (int e = d + 1; e < b.ndim; ++e) st *= b.shape[e];
-                const int64_t es = k < 2 ? 1 : (k == 2 && red == SKEL_RED_HIST256_SUM ? 4 : 8);
-                if (b.stride_bytes[d] != st * es && b.shape[d] > 1)
-                    return set_error(SKEL_ESHAPE, "request %d argument %d: not dense", r, k);
-            }
-    }
+    auto esize = [&](int k) -> int64_t { return k < 2 ? 1 : (k == 2 && red == SKEL_RED_HIST256_SUM ? 4 : 8); };
+    for (int k = 0; k < nargs; ++k)
+        if (!dense_strides(a[k], esize(k)))
+            return set_error(SKEL_ESHAPE, "request %d argument %d: not dense row-major", r, k);
     const skel_buffer &in = a[0], &out = a[1];
     if (in.dtype != SKEL_U8 || out.dtype != SKEL_U8 || in.ndim != 3 || out.ndim != 3 || in.shape[2] != 4 ||
         out.shape[0] != in.shape[0] || out.shape[1] != in.shape[1] || out.shape[2] != 4)
@@ -48,8 +52,22 @@ skel_status check_req(const skel_buffer* a, int nargs, int red, int r, bool inpl
         return set_error(SKEL_EUNSUPPORTED, "request %d: image of %lld x %lld is out of range", r, (long long)H,
                          (long long)W);
     if (W * H > 0 && (!in.data || !out.data)) return set_error(SKEL_EINVAL, "request %d: null image", r);
+    // A request's in and out are either the same buffer (pointwise chains
+    // only) or disjoint: a partial overlap would race with the stencil's halo
+    // reads of other tiles of the same persistent launch.
+    const Span si = span_of(in, 1), so = span_of(out, 1);
     if (in.data == out.data && W * H > 0 && !inplace_ok)
         return set_error(SKEL_EINVAL, "request %d: in-place run of a kernel with a stencil or a mirror", r);
+    if (in.data != out.data && spans_overlap(si, so))
+        return set_error(SKEL_EINVAL, "request %d: input and output overlap partially", r);
+    for (int k = 2; k < nargs; ++k) {
+        const Span sk = span_of(a[k], esize(k));
+        if (spans_overlap(sk, si) || spans_overlap(sk, so))
+            return set_error(SKEL_EINVAL, "request %d: reduce output %d overlaps an image", r, k);
+        for (int j = k + 1; j < nargs; ++j)
+            if (spans_overlap(sk, span_of(a[j], esize(j))))
+                return set_error(SKEL_EINVAL, "request %d: reduce outputs overlap", r);
+    }
     if (red == SKEL_RED_HIST256_SUM) {
         if (a[2].dtype != SKEL_U32 || a[2].ndim != 2 || a[2].shape[0] != 4 || a[2].shape[1] != 256 || !a[2].data)
             return set_error(SKEL_ESHAPE, "request %d: hist must be uint32 [4, 256]", r);
@@ -58,6 +76,40 @@ skel_status check_req(const skel_buffer* a, int nargs, int red, int r, bool inpl
     } else if (red == SKEL_RED_SUM) {
         if (a[2].dtype != SKEL_U64 || a[2].ndim != 1 || a[2].shape[0] != 4 || !a[2].data)
             return set_error(SKEL_ESHAPE, "request %d: sum must be uint64 [4]", r);
+    }
+    return SKEL_OK;
+}
+
+// Requests of one batch run in the same launch, in no particular order, so no
+// buffer a request writes (image out, hist, sum) may overlap any other
+// request's buffers; inputs may be shared.  Sweep over the spans sorted by
+// start: every overlapping pair involving a write is found through the span
+// reaching furthest so far (an in-place request's in == out counts as one
+// written span).
+skel_status check_disjoint(const skel_buffer* args, int nargs, int nreq, int red) {
+    struct Item {
+        Span sp;
+        int req;
+        bool write;
+    };
+    std::vector<Item> it;
+    it.reserve((size_t)nreq * nargs);
+    for (int r = 0; r < nreq; ++r) {
+        const skel_buffer* a = args + (size_t)r * nargs;
+        for (int k = 0; k < nargs; ++k) {
+            if (k == 0 && a[0].data == a[1].data) continue;   // in place: the output span covers it
+            const int64_t es = k < 2 ? 1 : (k == 2 && red == SKEL_RED_HIST256_SUM ? 4 : 8);
+            const Span sp = span_of(a[k], es);
+            if (sp.hi > sp.lo) it.push_back(Item{sp, r, k > 0});
+        }
+    }
+    std::sort(it.begin(), it.end(), [](const Item& x, const Item& y) { return x.sp.lo < y.sp.lo; });
+    const Item* far = nullptr;
+    for (const Item& c : it) {
+        if (far && c.sp.lo < far->sp.hi && (c.write || far->write))
+            return set_error(SKEL_EINVAL, "requests %d and %d: a written buffer overlaps another buffer", far->req,
+                             c.req);
+        if (!far || c.sp.hi > far->sp.hi) far = &c;
     }
     return SKEL_OK;
 }
@@ -107,7 +159,9 @@ extern "C" skel_status skel_batch_run(skel_plan p, const skel_buffer* args, int3
         HIP_TRY(hipGraphLaunch(p->bexec, s));
         return SKEL_OK;
     }
-    // New request set: lay out the work list, largest requests first.
+    // New request set (a replayed key was checked when it was laid out).
+    if (skel_status st = check_disjoint(args, nargs, nreq, red)) return st;
+    // Lay out the work list, largest requests first.
     std::vector<int> order(nreq);
     std::iota(order.begin(), order.end(), 0);
     std::stable_sort(order.begin(), order.end(), [&](int x, int y) {

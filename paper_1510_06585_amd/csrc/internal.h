@@ -102,6 +102,9 @@ struct Kernel {
     const char* name = "";
 };
 
+// True when b's strides describe a dense row-major buffer of esize-byte
+// elements (all zero, or exactly the dense strides; see plan.cpp).
+bool dense_strides(const skel_buffer& b, int64_t esize);
 skel_status derive_shape(const Linear& lin, const skel_buffer* proto, int32_t nargs, Shape& sh);
 int expected_nargs(const Linear& lin);
 skel_status resolve_config(const Linear& lin, const Shape& sh, const skel_plan_opts* opts, Config& cfg);

@@ -198,12 +198,23 @@ int expected_nargs(const Linear& L) {
     return 2;
 }
 
-static bool dense_ok(const skel_buffer& b, int64_t esize) {
+// Dense row-major strides (the only layout the kernels address).  An empty
+// buffer is dense whatever its strides.  Otherwise the dimensions of extent
+// > 1 either all have stride 0 (the shorthand for "dense") or each has exactly
+// its dense stride; a mix of zero and non-zero strides is rejected, since a
+// zero stride would make the kernels step past the caller's allocation.
+// Dimensions of extent <= 1 are never stepped, so their strides are ignored.
+bool dense_strides(const skel_buffer& b, int64_t esize) {
     for (int d = 0; d < b.ndim; ++d)
-        if (b.shape[d] == 0) return true;   // no elements: any strides describe the same (empty) buffer
+        if (b.shape[d] == 0) return true;
+    bool any_zero = false, any_set = false;
+    for (int d = 0; d < b.ndim; ++d)
+        if (b.shape[d] > 1) (b.stride_bytes[d] == 0 ? any_zero : any_set) = true;
+    if (!any_set) return true;
+    if (any_zero) return false;
     int64_t stride = esize;
     for (int d = b.ndim - 1; d >= 0; --d) {
-        if (b.stride_bytes[d] != 0 && b.stride_bytes[d] != stride && b.shape[d] > 1) return false;
+        if (b.shape[d] > 1 && b.stride_bytes[d] != stride) return false;
         stride *= b.shape[d];
     }
     return true;
@@ -229,7 +240,7 @@ static skel_status check_buf(const skel_buffer& b, int k, int dt, int ndim, cons
                              (long long)shape[d]);
     for (int d = 0; d < ndim; ++d)
         if (b.shape[d] < 0) return set_error(SKEL_ESHAPE, "argument %d: negative extent", k);
-    if (!dense_ok(b, dtype_size(dt))) return set_error(SKEL_ESHAPE, "argument %d: not dense row-major", k);
+    if (!dense_strides(b, dtype_size(dt))) return set_error(SKEL_ESHAPE, "argument %d: not dense row-major", k);
     return SKEL_OK;
 }
 

@@ -224,3 +224,86 @@ def test_empty_buffers_with_any_strides_compile():
     b.stride_bytes[0], b.stride_bytes[1], b.stride_bytes[2] = 2, 2, 1
     d = sk.Plan(sk.image_chain([("segment", {})]), [b, b]).describe()
     assert d["kernels"][0]["grid"] == 0
+
+
+def _dense(shape, dtype, addr):
+    """A skel_buffer over a fake device address with explicit dense strides
+    (only host-side checks run on it: every request below is rejected before
+    the library touches the device)."""
+    b = sk.proto(shape, dtype)
+    b.data = addr
+    es = {sk.U8: 1, sk.U32: 4, sk.U64: 8, sk.F32: 4, sk.F64: 8}[dtype]
+    st = es
+    for d in range(len(shape) - 1, -1, -1):
+        b.stride_bytes[d] = st
+        st *= shape[d]
+    return b
+
+
+def _img_req(base, H, W):
+    """in, out, hist, sum of one image request laid out back to back from base."""
+    n = H * W * 4
+    return [_dense([H, W, 4], sk.U8, base), _dense([H, W, 4], sk.U8, base + n),
+            _dense([4, 256], sk.U32, base + 2 * n), _dense([4], sk.U64, base + 2 * n + 4096)]
+
+
+def test_mixed_zero_strides_are_rejected():
+    # strides may be all zero (dense shorthand) or exactly dense; a zero stride
+    # next to non-zero ones would make the kernels read past the allocation
+    root = sk.image_chain(PIPE_NSBM, "hist_sum")
+    good = _img_req(1 << 40, 6, 5)
+    p = sk.Plan(root, good)
+    for bad_strides in ([0, 4, 1], [20, 0, 1], [20, 4, 0]):
+        a = _img_req(1 << 40, 6, 5)
+        a[0].stride_bytes[0], a[0].stride_bytes[1], a[0].stride_bytes[2] = bad_strides
+        with pytest.raises(sk.SkelError) as e:
+            sk.Plan(root, a)
+        assert e.value.status == sk.ESHAPE, bad_strides
+        with pytest.raises(sk.SkelError) as e:
+            p.run(a, stream=0)
+        assert e.value.status == sk.ESHAPE, bad_strides
+        with pytest.raises(sk.SkelError) as e:
+            p.batch_run([a], stream=0)
+        assert e.value.status == sk.ESHAPE, bad_strides
+    # a zero stride on an extent-1 dimension is never stepped and is accepted
+    one = sk.proto([1, 5, 4], sk.U8)
+    one.stride_bytes[0], one.stride_bytes[1], one.stride_bytes[2] = 0, 4, 1
+    sk.Plan(sk.image_chain(PIPE_NSBM), [one, one])
+    allz = sk.proto([6, 5, 4], sk.U8)
+    sk.Plan(sk.image_chain(PIPE_NSBM), [allz, allz])
+
+
+def test_batch_rejects_overlapping_requests():
+    root = sk.image_chain(PIPE_NSBM, "hist_sum")
+    p = sk.Plan(root, _img_req(1 << 40, 8, 8))
+    H, W = 8, 8
+    n = H * W * 4
+    # in and out of one request overlap partially
+    a = _img_req(1 << 40, H, W)
+    a[1].data = a[0].data + 16
+    with pytest.raises(sk.SkelError) as e:
+        p.batch_run([a], stream=0)
+    assert e.value.status == sk.EINVAL
+    # a reduce output inside an image
+    a = _img_req(1 << 40, H, W)
+    a[2].data = a[1].data + 64
+    with pytest.raises(sk.SkelError) as e:
+        p.batch_run([a], stream=0)
+    assert e.value.status == sk.EINVAL
+    # two requests writing the same histogram / one's output over another's input
+    a, b = _img_req(1 << 40, H, W), _img_req(1 << 41, H, W)
+    b[2].data = a[2].data
+    with pytest.raises(sk.SkelError) as e:
+        p.batch_run([a, b], stream=0)
+    assert e.value.status == sk.EINVAL
+    a, b = _img_req(1 << 40, H, W), _img_req(1 << 41, H, W)
+    b[1].data = a[0].data + n // 2
+    with pytest.raises(sk.SkelError) as e:
+        p.batch_run([a, b], stream=0)
+    assert e.value.status == sk.EINVAL
+    # a stencil chain cannot run in place
+    a = _img_req(1 << 40, H, W)
+    a[1].data = a[0].data
+    with pytest.raises(sk.SkelError) as e:
+        p.batch_run([a], stream=0)
+    assert e.value.status == sk.EINVAL
