@@ -11,7 +11,7 @@ requests, while Loop, FFT pipeline, Segmentation).
 
   python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-extras]
                   [--no-cpu-baseline] [--selector] [--profile-run] [--filter-pipeline-only]
-                  [--while-only]
+                  [--while-only] [--mlp-profile-run]
 """
 from __future__ import annotations
 
@@ -28,6 +28,9 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0                                   # MI355X HBM3E, GB/s
 VALU_LANE_OPS = 256 * 64 * 2.4e9                        # 256 CUs x 64 lanes x 2.4 GHz
 NBODY_LANE_OPS_PER_PAIR = 13                            # 13 VALU issues per pair, v_rsq_f32 included
+NBODY_FLOPS_PER_PAIR = 20                               # conventional flop count of one pair interaction
+FP32_PEAK_TFLOPS = 157.3                                # MI355X FP32 vector (packed FP32)
+FP32_NONPACKED_TFLOPS = 78.6                            # the same without packed FP32 instructions
 METRIC = "Gelem/s & % HBM roofline per skeleton; fused/learned vs plain speedup"
 PIPE_NSBM = [("noise", {"seed": 0x1510}), ("solarise", {}), ("blur5", {}), ("mirror", {})]
 PIPE_NSM = [("noise", {"seed": 0x1510}), ("solarise", {}), ("mirror", {})]
@@ -37,13 +40,36 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def timed_runs(fn, steps, warmup):
-    """Runs fn() warmup times untimed, then `steps` times bracketed by device
-    synchronisation; returns (wall seconds, event milliseconds)."""
+# Untimed load before every timed region, whatever --warmup says: the GPU
+# needs about 0.1 s of load to reach its working clocks (timed steps right
+# after 5 warm-up steps of the 8192^2 chain, ~1 ms of work, ran 10-15% slow).
+WARM_SECONDS = 0.3
+
+
+def warm_up(fn, warmup, min_seconds=WARM_SECONDS):
+    """fn() `warmup` times, then more calls (in groups of 4, synchronised)
+    until at least min_seconds of wall time have passed.  Returns the number
+    of calls made."""
     import torch
+    t0 = time.perf_counter()
+    n = 0
     for _ in range(warmup):
         fn()
+        n += 1
     torch.cuda.synchronize()
+    while time.perf_counter() - t0 < min_seconds:
+        for _ in range(4):
+            fn()
+            n += 1
+        torch.cuda.synchronize()
+    return n
+
+
+def timed_runs(fn, steps, warmup):
+    """Warms up (see warm_up), then runs fn() `steps` times bracketed by device
+    synchronisation; returns (wall seconds, event milliseconds)."""
+    import torch
+    warm_up(fn, warmup)
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
     t0 = time.perf_counter()
@@ -96,8 +122,10 @@ class HipEvents:
 
 def kernel_times(plan, bound, kernel, steps):
     """Durations (ms) of one kernel of a plan over `steps` runs, from HIP
-    events the plan records around that kernel on the launch stream."""
+    events the plan records around that kernel on the launch stream (after the
+    same warm-up floor as timed_runs)."""
     import torch
+    warm_up(lambda: plan.run(bound), 0)
     ev = HipEvents(steps)
     for i in range(steps):
         plan.kernel_events(kernel, *ev.pair(i))
@@ -186,7 +214,8 @@ def bench_fused_mapreduce_8192(steps, warmup, do_cpu):
     root = sk.image_chain(PIPE_NSBM, "hist_sum")
     fused = sk.Plan(root, args)
     plain = sk.Plan(root, args, {"fusion": sk.FUSE_OFF})
-    wall, ev_ms = timed_runs(lambda: fused.run(bound), steps, warmup)
+    warm_calls = warm_up(lambda: fused.run(bound), warmup)
+    wall, ev_ms = timed_runs(lambda: fused.run(bound), steps, 0)
     ms_step = wall * 1e3 / steps
     k_ts = sorted(kernel_times(fused, bound, 0, steps))
     k_ms = sum(k_ts) / len(k_ts)
@@ -223,6 +252,7 @@ def bench_fused_mapreduce_8192(steps, warmup, do_cpu):
                      "traffic": traffic, "kernel_ms": round(k_ms, 5), "kernel_ms_min": round(k_ts[0], 5),
                      "kernel_ms_median": round(k_ts[len(k_ts) // 2], 5), "algorithmic_bytes": int(algo)},
         "copy_reference_gbs": round(copy_gbs, 1),
+        "warmup_policy": {"steps": warmup, "min_seconds": WARM_SECONDS, "untimed_calls": warm_calls},
         "event_ms_per_step": round(ev_ms / steps, 5),
         "plain_ms_per_step": round(plain_ms, 5),
         "fused_vs_plain_speedup": round(plain_ms / (ev_ms / steps), 3),
@@ -270,11 +300,19 @@ def bench_nbody():
         res[f"{name}_ginteractions_s"] = round(pairs / (ms * 1e-3) / 1e9, 2)
         p.destroy()
     rate = float(N) * N * iters / (res["graph_fused_ms_per_loop"] * 1e-3)
-    peak = VALU_LANE_OPS / NBODY_LANE_OPS_PER_PAIR
-    res["roofline"] = {"bound": "alu", "achieved": round(rate / 1e9, 2), "peak": round(peak / 1e9, 2),
-                       "unit": "Ginteractions/s", "frac": round(rate / peak, 4),
-                       "note": "peak = 256 CUs x 64 lanes x 2.4 GHz / 13 VALU issues per pair"}
-    res["tflops_20flop_convention"] = round(rate * 20 / 1e12, 2)
+    tflops = rate * NBODY_FLOPS_PER_PAIR / 1e12
+    res["roofline"] = {"bound": "alu", "achieved": round(tflops, 2), "peak": FP32_PEAK_TFLOPS,
+                       "unit": "TFLOP/s", "frac": round(tflops / FP32_PEAK_TFLOPS, 4),
+                       "frac_of_non_packed_fp32_peak": round(tflops / FP32_NONPACKED_TFLOPS, 4),
+                       "note": f"{NBODY_FLOPS_PER_PAIR} flops per pair interaction by convention; peak = MI355X "
+                               f"published FP32 vector rate (packed FP32), {FP32_NONPACKED_TFLOPS} without "
+                               f"packed FP32 instructions, which this build does not use"}
+    issue_peak = VALU_LANE_OPS / NBODY_LANE_OPS_PER_PAIR
+    res["issue_efficiency"] = {"achieved_ginteractions_s": round(rate / 1e9, 2),
+                               "issue_bound_ginteractions_s": round(issue_peak / 1e9, 2),
+                               "frac": round(rate / issue_peak, 4),
+                               "note": "the kernel's own instruction count: 13 VALU issues per pair "
+                                       "(v_rsq_f32 included) on 256 CUs x 64 lanes x 2.4 GHz"}
     return res
 
 
@@ -387,7 +425,12 @@ def bench_fft():
         res[f"{name}_pass_traffic_gbs"] = round(passes * algo / (ms * 1e-3) / 1e9, 1)
         p.destroy()
     res["fused_vs_plain_speedup"] = round(res["plain_ms"] / res["fused_ms"], 3)
-    res["fused_hbm_frac_of_pass_traffic"] = round(res["fused_pass_traffic_gbs"] / HBM_PEAK_GBS, 4)
+    # the chain's own algorithmic bytes: the input read once and the output
+    # written once (every extra pass is the method's cost, not the workload's)
+    res["chain_algorithmic_bytes"] = int(algo)
+    res["fused_chain_hbm_gbs"] = round(algo / (res["fused_ms"] * 1e-3) / 1e9, 1)
+    res["fused_chain_hbm_frac"] = round(res["fused_chain_hbm_gbs"] / HBM_PEAK_GBS, 4)
+    res["fused_pass_traffic_frac"] = round(res["fused_pass_traffic_gbs"] / HBM_PEAK_GBS, 4)
     return res
 
 
@@ -478,6 +521,27 @@ def profile_run(steps):
                       "copy_bytes_per_launch": 2 * 8192 * 8192 * 4}), flush=True)
 
 
+def mlp_profile_run(n=16384, reps=3):
+    """Workload of the MFMA counter pass: the cost-model MLP's forward and
+    gradient kernels `reps` times each on n seeded random samples."""
+    import torch
+    import paper_1510_06585_amd as sk
+    g = torch.Generator(device="cuda")
+    g.manual_seed(1)
+    P = sk.mlp_param_count()
+    params = (torch.rand(P, device="cuda", generator=g) - 0.5) * 0.2
+    X = torch.rand(n, 24, device="cuda", generator=g)
+    t = torch.rand(n, device="cuda", generator=g)
+    y = torch.empty(n, device="cuda")
+    grad = torch.empty(P, device="cuda")
+    loss = torch.empty(1, device="cuda")
+    for _ in range(reps):
+        sk.mlp_forward(params, X, y)
+        sk.mlp_grad(params, X, t, grad, loss)
+    torch.cuda.synchronize()
+    print(json.dumps({"mlp_profile_run": {"samples": n, "reps": reps}}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -490,6 +554,8 @@ def main():
     ap.add_argument("--profile-run", action="store_true", help="short run for rocprofv3 counter passes")
     ap.add_argument("--filter-pipeline-only", action="store_true",
                     help="only the 1024x1024 filter pipeline, plain and fused (for a per-stage kernel trace)")
+    ap.add_argument("--mlp-profile-run", action="store_true",
+                    help="only the cost-model MLP forward and gradient kernels on 16384 samples (MFMA counters)")
     ap.add_argument("--while-only", action="store_true",
                     help="only the 8192x8192 x 10 while Loop against its host-checked and unchecked forms "
                          "(for a kernel trace)")
@@ -510,6 +576,9 @@ def main():
     sk.lib()
     if a.profile_run:
         profile_run(a.steps)
+        return
+    if a.mlp_profile_run:
+        mlp_profile_run()
         return
     if a.filter_pipeline_only:
         print(json.dumps(bench_filter_pipeline_1024()), flush=True)

@@ -95,7 +95,7 @@ COMMAND_FILTER_PIPELINE = ("rocprofv3 --kernel-trace --stats -d DIR -o filter102
 COMMAND_WHILE = ("rocprofv3 --kernel-trace --stats -d DIR -o while8192 --output-format csv -- python3 bench.py "
                  "--while-only")
 COMMAND_MLP = ("rocprofv3 --pmc SQ_INSTS_VALU_MFMA_MOPS_F32 SQ_VALU_MFMA_BUSY_CYCLES SQ_INSTS_VALU SQ_BUSY_CYCLES "
-               "-d DIR -o mfma --output-format csv -- python3 -m paper_1510_06585_amd.mlp_probe")
+               "-d DIR -o mfma --output-format csv -- python3 bench.py --mlp-profile-run")
 HBM_PEAK_GBS = 8000.0
 NBODY_PEAK_GPAIRS = 256 * 64 * 2.4 / 13.0   # 13 VALU issues per pair
 
@@ -232,7 +232,7 @@ def main():
         fwd_flops = 2 * n * (24 * 64 + 64 * 64 + 64)
         ml = ["# rocprofv3 counters: cost-model MLP kernels on the matrix cores (16384 samples, 24->64->64->1)", "",
               "Command (repository root on the MI355X host, TMPDIR=/tmp):", "", "```", COMMAND_MLP, "```", "",
-              "The script runs `skel_mlp_forward` and `skel_mlp_grad` three times each on 16384 random "
+              "`bench.py --mlp-profile-run` runs `skel_mlp_forward` and `skel_mlp_grad` three times each on 16384 random "
               f"samples.  The forward pass's layer products are {fwd_flops} flops; one "
               "SQ_INSTS_VALU_MFMA_MOPS_F32 count is 512 flops.", "",
               "| kernel | counter | mean per dispatch |", "|---|---|---|"]

@@ -83,6 +83,24 @@ def test_sum_cancellation_and_all_ones():
     assert abs(s - S) <= 1e-5 * A
 
 
+def test_sum_without_cancellation_at_the_bench_size():
+    """5 x 10^7 values uniform in [0, 1) (no cancellation, so the plain
+    relative error is well conditioned): |S - S_ref| / |S_ref| <= 1e-5, after
+    a two-stage saxpy chain and after a reversal alone."""
+    n = 50_000_000
+    v = synth.vector(21, n, 0.0, 1.0)
+    out, s = run_chain([("mirror", {})], v, [], "sum")
+    S, A = oracle.run_f32_chain(v, [("mirror", {})], [], "sum")[1]
+    assert S == A and abs(s - S) / abs(S) <= 1e-5, (s, S)
+    w1, w2 = synth.vector(22, n, 0.0, 1.0), synth.vector(23, n, 0.0, 1.0)
+    st = [("saxpy", {"a": 0.5}), ("saxpy", {"a": 1.25})]
+    ref = oracle.run_f32_chain(v, st, [w1, w2], "sum")
+    out, s = run_chain(st, v, [w1, w2], "sum")
+    assert out.tobytes() == ref[0].tobytes()
+    S = ref[1][0]
+    assert S > 0 and abs(s - S) / abs(S) <= 1e-5, (s, S)
+
+
 def test_random_vector_compositions():
     rng = np.random.default_rng(synth.SEED_SELECT + 1)
     done = 0
