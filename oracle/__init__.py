@@ -181,19 +181,55 @@ _CMP = {">": lambda v, t: v > t, ">=": lambda v, t: v >= t, "<": lambda v, t: v 
 
 
 def run_image_while(img: np.ndarray, stages, reduce: str, channel: int, cmp: str, threshold: int,
-                    max_iterations: int):
-    """While Loop over a MapReduce body (Sec. 2.1, Loop: while loops; its state holds
-    the stop condition): run the body (``stages`` then ``reduce``) on the current
-    image, count the iteration, and repeat while ``sum[channel] cmp threshold``
-    holds and fewer than ``max_iterations`` iterations have run (the body runs at
-    least once).  Returns ``(out, hist, sum, count)``."""
+                    max_iterations: int, kind: str = "value", carried=(), init_hist=None, init_sum=None):
+    """While Loop over a MapReduce body (Sec. 2.1, Loop: while loops whose state
+    holds the stop condition, the items updated after every iteration, and
+    whether that update needs a global synchronisation; Sec. 3.4, partial
+    results merged by a merging function).
+
+    Each iteration runs the body (``stages`` then ``reduce``) on the current
+    image, giving that iteration's image, histogram h_i and channel sums s_i,
+    and counts itself.  The loop repeats while the condition holds and fewer
+    than ``max_iterations`` iterations have run (the body runs at least once):
+
+    * ``kind="value"``: ``s_i[channel] cmp threshold``;
+    * ``kind="delta"`` (convergence of the reduction):
+      ``|s_i[channel] - s_(i-1)[channel]| cmp threshold``; the first iteration
+      has no predecessor and always continues.
+
+    The condition reads the iteration's own sums.  The loop state's outputs
+    are the last image and the reduce outputs: an output named in ``carried``
+    (``"hist"``, ``"sum"``) is carried across iterations and merged by addition,
+    starting from ``init_hist`` / ``init_sum`` (zeros if None); any other
+    reduce output is the last iteration's.  Returns ``(out, hist, sum, count)``
+    (``hist`` is None for ``reduce="sum"``)."""
+    if kind not in ("value", "delta"):
+        raise ValueError(kind)
     cur = _img(img)
     count = 0
+    acc_h = np.zeros((4, 256), np.uint64) if init_hist is None else np.asarray(init_hist).astype(np.uint64)
+    acc_s = np.zeros(4, np.uint64) if init_sum is None else np.asarray(init_sum).astype(np.uint64)
+    prev = None
     while True:
         cur, hist, s = run_image_pipeline(cur, stages, reduce)
         count += 1
-        if count >= max_iterations or not _CMP[cmp](int(s[channel]), int(threshold)):
-            return cur, hist, s, count
+        if hist is not None:
+            acc_h = acc_h + hist.astype(np.uint64)
+        acc_s = acc_s + s
+        v = int(s[channel])
+        if kind == "value":
+            go = _CMP[cmp](v, int(threshold))
+        else:
+            go = True if prev is None else _CMP[cmp](abs(v - prev), int(threshold))
+        prev = v
+        if count >= max_iterations or not go:
+            break
+    out_h = None
+    if hist is not None:
+        # uint32 outputs wrap modulo 2^32 like the device counters
+        out_h = (acc_h % (1 << 32)).astype(np.uint32) if "hist" in carried else hist
+    out_s = acc_s if "sum" in carried else s
+    return cur, out_h, out_s, count
 
 
 # ---------------------------------------------------------- Segmentation stages

@@ -214,3 +214,83 @@ def test_while_loop_matches_library_iteration(orc):
     out, h, s, n = orc.run_image_while(img, [("blur5", {})], "hist_sum", 1, ">", T, 8)
     assert n == stop
     assert (out.astype(np.int64) == seq[stop - 1][0]).all() and (s.astype(np.int64) == seq[stop - 1][1]).all()
+
+
+def _scipy_blur_iterates(img, n):
+    """The first n iterates of the 5x5 box blur written with scipy's 'nearest'
+    correlation and one floor division, with each iterate's channel sums and
+    per-channel histograms (numpy bincount), independent of the oracle."""
+    from scipy.ndimage import correlate
+    cur = img.astype(np.int64)
+    out = []
+    for _ in range(n):
+        cur = np.stack([correlate(cur[..., c], np.ones((5, 5), np.int64), mode="nearest") // 25
+                        for c in range(4)], axis=-1)
+        h = np.stack([np.bincount(cur[..., c].ravel(), minlength=256) for c in range(4)])
+        out.append((cur.copy(), cur.reshape(-1, 4).sum(0), h))
+    return out
+
+
+def test_while_delta_condition_and_carried_merge_on_constant_image(orc):
+    """On a constant image the blur changes nothing: the first iteration has no
+    predecessor and continues, the second sees a change of 0 and stops under
+    'continue while |change| > 0'.  Carried outputs are the sum of the two
+    iterations' results (merge by addition); uncarried ones the last."""
+    H, W, v = 6, 9, 40
+    img = np.full((H, W, 4), v, np.uint8)
+    body = [("blur5", {})]
+    out, h, s, n = orc.run_image_while(img, body, "hist_sum", 0, ">", 0, 10, kind="delta")
+    assert n == 2 and (out == img).all()
+    assert int(s[0]) == H * W * v and int(h[1, v]) == H * W
+    out, h, s, n = orc.run_image_while(img, body, "hist_sum", 0, ">", 0, 10, kind="delta",
+                                       carried=("hist", "sum"))
+    assert n == 2 and all(int(s[c]) == 2 * H * W * v for c in range(4))
+    assert int(h[3, v]) == 2 * H * W and int(h.sum()) == 2 * 4 * H * W
+    # only the sums carried: the histogram is the last iteration's
+    _, h, s, n = orc.run_image_while(img, body, "hist_sum", 0, ">", 0, 10, kind="delta", carried=("sum",))
+    assert int(s[2]) == 2 * H * W * v and int(h[2, v]) == H * W
+    # a limit of 1 stops after the first iteration whatever the condition
+    _, _, s, n = orc.run_image_while(img, body, "sum", 0, ">", 0, 1, kind="delta", carried=("sum",))
+    assert n == 1 and int(s[0]) == H * W * v
+
+
+def test_while_delta_and_carried_match_explicit_iteration(orc):
+    """Random image, blur body: the loop stops at the first iteration i >= 2
+    whose channel-1 sum changed by at most T since iteration i - 1; carried
+    sums and histograms equal the totals over the explicit iterates."""
+    img = np.random.default_rng(18).integers(0, 256, (21, 33, 4), dtype=np.uint8)
+    seq = _scipy_blur_iterates(img, 12)
+    sums = [int(t[1][1]) for t in seq]
+    deltas = [abs(sums[i] - sums[i - 1]) for i in range(1, 12)]
+    T = sorted(deltas)[len(deltas) // 2]               # stops somewhere inside the 12 iterations
+    stop = next(i for i in range(1, 12) if abs(sums[i] - sums[i - 1]) <= T) + 1
+    assert 2 <= stop <= 12
+    out, h, s, n = orc.run_image_while(img, [("blur5", {})], "hist_sum", 1, ">", T, 12, kind="delta",
+                                       carried=("hist", "sum"))
+    assert n == stop
+    assert (out.astype(np.int64) == seq[stop - 1][0]).all()
+    assert (s.astype(np.int64) == sum(t[1] for t in seq[:stop])).all()
+    assert (h.astype(np.int64) == sum(t[2] for t in seq[:stop])).all()
+    # uncarried: the last iterate's results
+    _, h, s, n = orc.run_image_while(img, [("blur5", {})], "hist_sum", 1, ">", T, 12, kind="delta")
+    assert n == stop and (s.astype(np.int64) == seq[stop - 1][1]).all() and (h == seq[stop - 1][2]).all()
+    # the value condition is unaffected by carrying (it reads the iteration's own sums)
+    Tv = sums[3]
+    _, _, s, n = orc.run_image_while(img, [("blur5", {})], "sum", 1, ">", Tv, 12, carried=("sum",))
+    nv = next(i for i, x in enumerate(sums) if not x > Tv) + 1
+    assert n == nv and (s.astype(np.int64) == sum(t[1] for t in seq[:nv])).all()
+
+
+def test_while_carried_outputs_start_from_the_callers_values(orc):
+    """Carried outputs start from the loop state the caller passes in; the
+    uint32 histogram counters wrap modulo 2^32 as the device's do."""
+    img = np.full((4, 5, 4), 9, np.uint8)
+    init_h = np.zeros((4, 256), np.uint32)
+    init_h[0, 9] = 2 ** 32 - 7
+    init_h[2, 200] = 5
+    init_s = np.array([1, 2, 3, 2 ** 63], np.uint64)
+    _, h, s, n = orc.run_image_while(img, [("blur5", {})], "hist_sum", 0, ">=", 0, 3,
+                                     carried=("hist", "sum"), init_hist=init_h, init_sum=init_s)
+    assert n == 3
+    assert int(h[0, 9]) == (2 ** 32 - 7 + 3 * 20) % 2 ** 32 and int(h[2, 200]) == 5 and int(h[1, 9]) == 60
+    assert [int(x) for x in s] == [1 + 540, 2 + 540, 3 + 540, 2 ** 63 + 540]
