@@ -298,6 +298,26 @@ skel_status skel_plan_run_event(skel_plan plan, const skel_buffer* args, int32_t
 skel_status skel_batch_run(skel_plan plan, const skel_buffer* args, int32_t nargs,
                            int32_t nreq, void* stream);
 
+/* Allocation-free execution request, for callers that cannot allocate device
+ * memory while they run (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc).  Same arguments, checks, ordering and
+ * results as skel_plan_run, but the plan's device scratch (intermediate
+ * images / vectors / volumes of unfused plans, fp32 reduce partials, image
+ * histogram rows) is carved out of one static device array of
+ * SKEL_NOALLOC_SCRATCH_BYTES per GPU, which the library holds from module
+ * load until the process ends; the call itself never allocates (no hipMalloc,
+ * hipFree or host allocation).  Covers image chains (not while Loops), fp32
+ * chains and gray chains; N-body Loops, FFT chains and while Loops are
+ * SKEL_EUNSUPPORTED, and so is a plan whose scratch exceeds the array
+ * (every fused image chain up to the 2 GiB image limit fits; unfused plans
+ * need two intermediate images).  Every call on one GPU shares that GPU's
+ * array and leaves its contents behind: calls that overlap in time on one GPU
+ * (different streams, or different host threads) race and must be ordered by
+ * the caller, e.g. by using one stream.  The device address of the array is
+ * looked up by skel_init(device), or by this call's first use on a device. */
+#define SKEL_NOALLOC_SCRATCH_BYTES (32u << 20)
+skel_status skel_plan_run_noalloc(skel_plan plan, const skel_buffer* args, int32_t nargs, void* stream);
+
 /* Writes a one-line JSON description (linearised stages, kernels and their
  * stages, configuration) into buf (NUL-terminated, truncated to len). */
 skel_status skel_plan_describe(skel_plan plan, char* buf, size_t len);

@@ -423,6 +423,86 @@ skel_status ensure_resources(skel_plan p) {
 
 skel_status skel_ensure_resources(skel_plan p) { return ensure_resources(p); }
 
+// Runs from caller-provided device scratch (the allocation-free entry point):
+// the buffers ensure_resources would allocate -- intermediate images, vectors
+// or volumes between unfused kernels, fp32 reduce partials and image histogram
+// rows -- are carved out of one region in 256-byte aligned pieces.  Plans that
+// need anything else (an N-body graph, FFT twiddles uploaded from the host, a
+// while Loop's pinned flag and events) are SKEL_EUNSUPPORTED.
+namespace {
+size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
+}  // namespace
+
+skel_status noalloc_prepare(skel_plan p, const skel_buffer* args, int32_t nargs, size_t cap, NoallocLayout& L) {
+    skel_status st = check_args(p, args, nargs);
+    if (st) return st;
+    if ((st = check_aliasing(p, args))) return st;
+    const Domain dom = p->lin.dom;
+    if (dom == DOM_NBODY || dom == DOM_C32 || (dom == DOM_U8 && p->lin.is_while) ||
+        (dom != DOM_U8 && dom != DOM_F32 && dom != DOM_GRAY))
+        return set_error(SKEL_EUNSUPPORTED,
+                         "allocation-free runs cover image, fp32 and gray chains (not N-body loops, FFT chains or "
+                         "while Loops)");
+    L = NoallocLayout{};
+    int nscr = 0;
+    for (const Kernel& k : p->kernels) nscr = std::max(nscr, k.dst >= 0 ? k.dst + 1 : 0);
+    size_t bytes = 0;
+    if (dom == DOM_U8) bytes = (size_t)(p->sh.W * p->sh.H * 4);
+    if (dom == DOM_F32) bytes = (size_t)(p->sh.n * 4);
+    if (dom == DOM_GRAY) bytes = (size_t)p->sh.n;
+    size_t off = 0;
+    L.nimg = nscr;
+    for (int k = 0; k < nscr; ++k) {
+        L.off_img[k] = off;
+        off += align256(std::max<size_t>(bytes, 16));
+    }
+    if (dom == DOM_F32 && p->lin.red >= 0) {
+        int g = 1;
+        for (const Kernel& k : p->kernels)
+            if (k.reduce) g = std::max(g, k.grid);
+        L.off_partials = off;
+        L.has_partials = true;
+        off += align256(sizeof(float) * g);
+    }
+    if (dom == DOM_U8 && p->lin.red >= 0) {
+        for (const Kernel& k : p->kernels)
+            if (k.reduce) {
+                L.off_hrows = off;
+                L.has_hrows = true;
+                off += align256(sizeof(uint32_t) * 4 * (size_t)k.bins * (size_t)std::max(1, k.grid));
+            }
+    }
+    L.total = off;
+    if (off > cap)
+        return set_error(SKEL_EUNSUPPORTED,
+                         "this plan needs %zu bytes of device scratch; the allocation-free entry point holds %zu "
+                         "(fuse the chain or use skel_plan_run)",
+                         off, cap);
+    return SKEL_OK;
+}
+
+skel_status noalloc_run(skel_plan p, const skel_buffer* args, void* stream, char* region, const NoallocLayout& L) {
+    void* saved_scr[2] = {p->scratch[0], p->scratch[1]};
+    float* saved_partials = p->partials;
+    uint32_t* saved_hrows = p->hrows;
+    for (int k = 0; k < L.nimg; ++k) p->scratch[k] = region + L.off_img[k];
+    if (L.has_partials) p->partials = (float*)(region + L.off_partials);
+    if (L.has_hrows) p->hrows = (uint32_t*)(region + L.off_hrows);
+    const hipStream_t s = S(stream);
+    skel_status st = SKEL_OK;
+    switch (p->lin.dom) {
+        case DOM_U8: st = run_image(p, args, s); break;
+        case DOM_F32: st = run_vector(p, args, s); break;
+        case DOM_GRAY: st = run_gray(p, args, s); break;
+        default: st = set_error(SKEL_EUNSUPPORTED, "plan domain not covered by the allocation-free entry point");
+    }
+    p->scratch[0] = saved_scr[0];
+    p->scratch[1] = saved_scr[1];
+    p->partials = saved_partials;
+    p->hrows = saved_hrows;
+    return st;
+}
+
 extern "C" {
 
 skel_status skel_init(int32_t device) {
@@ -435,7 +515,7 @@ skel_status skel_init(int32_t device) {
     HIP_TRY(hipGetDeviceProperties(&prop, device));
     if (strncmp(prop.gcnArchName, "gfx950", 6) != 0)
         return set_error(SKEL_EUNSUPPORTED, "device %d is %s; this library is built for gfx950", device, prop.gcnArchName);
-    return SKEL_OK;
+    return noalloc_setup(device);
 }
 
 skel_status skel_map(int32_t op, const skel_params* p, skel_node* out) {

@@ -160,3 +160,22 @@ struct skel_plan_s {
 };
 
 skel_status skel_ensure_resources(skel_plan p);
+
+// Allocation-free runs (skel_plan_run_noalloc): where each scratch buffer of a
+// plan sits in one caller-provided device region.
+struct NoallocLayout {
+    int nimg = 0;
+    size_t off_img[2] = {0, 0};
+    bool has_partials = false, has_hrows = false;
+    size_t off_partials = 0, off_hrows = 0;
+    size_t total = 0;
+};
+// Checks the arguments as skel_plan_run does, then lays out the plan's scratch;
+// SKEL_EUNSUPPORTED if the plan needs other resources or more than cap bytes.
+skel_status noalloc_prepare(skel_plan p, const skel_buffer* args, int32_t nargs, size_t cap, NoallocLayout& L);
+// Enqueues the plan's kernels with its scratch in `region` (device memory of
+// at least L.total bytes); the plan's own scratch pointers are left as they were.
+skel_status noalloc_run(skel_plan p, const skel_buffer* args, void* stream, char* region, const NoallocLayout& L);
+// Resolves the device address of the static scratch array on `device` (which
+// must be current) once; later calls are no-ops.
+skel_status noalloc_setup(int device);

@@ -88,6 +88,7 @@ _SIGS = {
                                            ctypes.POINTER(PlanOpts), ctypes.POINTER(_vp)]),
     "skel_plan_run": (ctypes.c_int32, [_vp, ctypes.POINTER(Buffer), ctypes.c_int32, _vp]),
     "skel_plan_run_event": (ctypes.c_int32, [_vp, ctypes.POINTER(Buffer), ctypes.c_int32, _vp, _vp]),
+    "skel_plan_run_noalloc": (ctypes.c_int32, [_vp, ctypes.POINTER(Buffer), ctypes.c_int32, _vp]),
     "skel_batch_run": (ctypes.c_int32, [_vp, ctypes.POINTER(Buffer), ctypes.c_int32, ctypes.c_int32, _vp]),
     "skel_plan_describe": (ctypes.c_int32, [_vp, ctypes.c_char_p, ctypes.c_size_t]),
     "skel_plan_destroy": (ctypes.c_int32, [_vp]),
@@ -323,6 +324,12 @@ class Plan:
     def run(self, args, stream=None):
         arr, n = _buf_array(args)
         _check(lib().skel_plan_run(self._h, arr, n, _stream_handle(stream)))
+
+    def run_noalloc(self, args, stream=None):
+        """skel_plan_run with the plan's scratch in the library's static
+        per-GPU array (no allocation by the call)."""
+        arr, n = _buf_array(args)
+        _check(lib().skel_plan_run_noalloc(self._h, arr, n, _stream_handle(stream)))
 
     def run_event(self, args, event, stream=None):
         arr, n = _buf_array(args)
