@@ -131,9 +131,16 @@ typedef struct skel_params {
 } skel_params;
 
 /* Loop state (Sec. 2.1: stop condition, items updated per iteration, whether
- * the update needs a global synchronisation).  Only counted loops are
- * implemented: iterations >= 0.  carried_mask (bit k = argument k is carried
- * from one iteration to the next) and global_sync are recorded and reported
+ * the update needs a global synchronisation).  iterations >= 0 is the count
+ * of a counted loop and the limit of a while Loop.  carried_mask: bit k =
+ * argument k of the plan is loop state carried from one iteration to the
+ * next.  A loop's image, vector or body positions are always carried (each
+ * iteration's output feeds the next).  In a while Loop a set bit on a reduce
+ * output (hist, sum) makes that output accumulate: every iteration's partial
+ * result is merged into it by addition (the merging function of Sec. 3.4),
+ * starting from the buffer's content when the run starts; a clear bit leaves
+ * the last iteration's result.  Bits beyond the plan's arguments, or on a
+ * while Loop's count, are SKEL_EINVAL.  global_sync is recorded and reported
  * by skel_plan_describe; every iteration boundary is a device-wide ordering
  * point regardless. */
 typedef struct skel_loop_state {
@@ -143,21 +150,29 @@ typedef struct skel_loop_state {
 } skel_loop_state;
 
 /* Stop condition of a while Loop (Sec. 2.1: Loop covers while loops; the
- * state holds the stoppage condition).  After every iteration the loop
- * continues while  sum[channel] <cmp> threshold  holds for the uint64
- * channel sums of the body's reduce output, and fewer than the state's
- * `iterations` iterations have run.  The condition is evaluated on the device;
- * the host enqueues blocks of check_every iterations (0 = 8) and, after
- * enqueuing a block, reads the one-word flag left by the block before it to
- * decide whether to enqueue more (a block enqueued after the condition failed
- * does no work). */
+ * state holds the stoppage condition).  After every iteration i the loop
+ * continues while fewer than the state's `iterations` iterations have run and,
+ * with s_i the iteration's own uint64 channel sums (before any merge into a
+ * carried output),
+ *   kind SKEL_COND_VALUE:  s_i[channel] <cmp> threshold
+ *   kind SKEL_COND_DELTA:  |s_i[channel] - s_(i-1)[channel]| <cmp> threshold
+ *                          (convergence of the reduction; iteration 0 has no
+ *                          predecessor and always continues).
+ * The condition is evaluated on the device.  check_every > 0: the host
+ * enqueues blocks of check_every iterations and, after enqueuing a block,
+ * reads the one-word flag left by the block before it to decide whether to
+ * enqueue more (a block enqueued after the condition failed does no work);
+ * 0 means 8.  check_every < 0: fully asynchronous -- the run enqueues all
+ * `iterations` guarded iterations and returns without waiting; iterations
+ * after the stop do no work beyond a guard test. */
 enum { SKEL_CMP_GT = 0, SKEL_CMP_GE = 1, SKEL_CMP_LT = 2, SKEL_CMP_LE = 3 };
+enum { SKEL_COND_VALUE = 0, SKEL_COND_DELTA = 1 };
 typedef struct skel_loop_cond {
     int32_t channel;      /* 0..3 */
     int32_t cmp;          /* SKEL_CMP_* */
     uint64_t threshold;
-    int32_t check_every;  /* iterations between host checks of the device flag; 0 = 8 */
-    int32_t reserved;
+    int32_t check_every;  /* > 0: iterations between host checks; 0 = 8; < 0 = no host checks */
+    int32_t kind;         /* SKEL_COND_VALUE or SKEL_COND_DELTA */
 } skel_loop_cond;
 
 /* -------------------------------------------------------- plan options */
@@ -229,16 +244,18 @@ skel_status skel_loop(skel_node body, const skel_loop_state* st, skel_node* out)
  * paper evaluates a Loop's condition and updates its state on the host,
  * Sec. 3.1; here both stay on the device).  body must be a MapReduce over an
  * image chain (SKEL_RED_HIST256_SUM or SKEL_RED_SUM); st->iterations >= 1 is
- * the iteration limit; carried_mask and global_sync are recorded.  Valid only
- * at the root of a plan.  A run computes
- *     x = in; count = 0;
- *     do { (x, hist, sum) = body(x); ++count; }
- *     while (count < st->iterations && sum[cond->channel] <cmp> threshold);
- * and writes out = x, hist/sum of the last iteration and count.  Plan
- * arguments: in u8 [H,W,4], out u8 [H,W,4], [hist u32 [4,256],] sum u64 [4],
- * count u32 [1]; in and out must not overlap.  Unlike other runs, a run of a
- * while plan blocks the host: after enqueuing each block of
- * cond->check_every iterations it waits for the previous block to finish. */
+ * the iteration limit.  Valid only at the root of a plan.  A run computes
+ *     x = in; count = 0; H = hist; S = sum;           (caller's initial state)
+ *     do { (x, h, s) = body(x); ++count;
+ *          H = carried(hist) ? H + h : h;  S = carried(sum) ? S + s : s; }
+ *     while (count < st->iterations && cond(s));
+ * and writes out = x, hist = H, sum = S and count (uint32 counters and uint64
+ * sums wrap).  Plan arguments: in u8 [H,W,4], out u8 [H,W,4],
+ * [hist u32 [4,256],] sum u64 [4], count u32 [1]; no two may overlap.  With
+ * cond->check_every >= 0 a run blocks the host: after enqueuing each block of
+ * check_every iterations it waits for the previous block to finish; with
+ * check_every < 0 it is asynchronous like every other run.  Errors:
+ * SKEL_EINVAL for a bad channel, cmp, kind, limit or carried_mask bit. */
 skel_status skel_loop_while(skel_node body, const skel_loop_state* st, const skel_loop_cond* cond,
                             skel_node* out);
 
@@ -374,6 +391,27 @@ skel_status skel_tune(skel_node root, const skel_buffer* args, int32_t nargs, co
 skel_status skel_tune_pruned(skel_node root, const skel_buffer* args, int32_t nargs, const char* db_path,
                              int32_t reps, double precision_us, double occ_threshold, skel_plan_opts* best,
                              double* best_us, int32_t* timed);
+
+/* Auto Tuner for batched runs (Sec. 2.2 applied to the batch execution
+ * model of Sec. 2): times skel_batch_run of the request set args[r*nargs+k]
+ * (nreq requests shaped as for skel_batch_run) over tile height x work-group
+ * size of the fully fused plan of `root` (the only partition a persistent
+ * batched launch holds): tile heights {8, 12, 16, 24, 31, 40, 48, 64, 96,
+ * 128} rows x work-groups of {64, 128, 256} threads (1, 2 or 4 adjacent
+ * tiles per group), each with 3 warm-up runs and the median of `reps` timed
+ * runs (reps <= 0: 10).  pruned == 0 times every point; otherwise the walk of
+ * Algorithm 1: sizes in non-increasing order of resident wavefronts per CU,
+ * stopping at the first size that does not improve, and per size tile
+ * heights increasing while each improves by at least precision_us.  Appends
+ * one row per timed point to db_path (may be NULL) in skel_tune's format,
+ * after a provenance line; the key starts with "batch<nreq>|px<pixels>|" and
+ * the features describe a square image of the batch's total pixel count.
+ * Writes the fastest options to *best (fusion ON, tile_h, wg), its median to
+ * *best_us and the number of points timed to *timed (both may be NULL).
+ * Synchronises the device; the requests' outputs are overwritten. */
+skel_status skel_tune_batch(skel_node root, const skel_buffer* args, int32_t nargs, int32_t nreq,
+                            const char* db_path, int32_t reps, int32_t pruned, double precision_us,
+                            skel_plan_opts* best, double* best_us, int32_t* timed);
 
 /* Number of valid configurations skel_tune would time exhaustively for
  * (root, shapes), i.e. the cost model's candidate set. */

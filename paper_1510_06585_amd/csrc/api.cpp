@@ -181,19 +181,44 @@ skel_status run_image(skel_plan p, const skel_buffer* args, hipStream_t s) {
 // waits, and a block enqueued after the condition failed runs only guarded
 // no-op kernels.  A final guarded copy moves a result that ended in the
 // second image.
+//
+// Carried reduce outputs (a carried_mask bit on hist or sum): the iteration's
+// kernels write that output into the plan's iteration buffer instead, and the
+// step kernel adds it to the caller's buffer, which is never cleared, so the
+// result is the caller's initial content plus every iteration's partial
+// result (the merge by addition of Sec. 3.4).  The condition always reads the
+// iteration's own sums.  check_every < 0: the whole limit is enqueued with no
+// host read-back, so the run is as asynchronous as any other.
 skel_status run_image_while(skel_plan p, const skel_buffer* args, hipStream_t s) {
     const Linear& L = p->lin;
     const int nargs = (int)p->proto.size();
+    const int sum_arg = L.red == SKEL_RED_HIST256_SUM ? 3 : 2;
     uint32_t* hist = L.red == SKEL_RED_HIST256_SUM ? (uint32_t*)args[2].data : nullptr;
-    uint64_t* sum = L.red == SKEL_RED_HIST256_SUM ? (uint64_t*)args[3].data : (uint64_t*)args[2].data;
+    uint64_t* sum = (uint64_t*)args[sum_arg].data;
     uint32_t* count = (uint32_t*)args[nargs - 1].data;
+    const bool carry_hist = hist && ((L.loop_carried >> 2) & 1u);
+    const bool carry_sum = (L.loop_carried >> sum_arg) & 1u;
+    uint32_t* it_hist = carry_hist ? p->witer_hist : hist;
+    uint64_t* it_sum = carry_sum ? p->witer_sum : sum;
+    WhileMerge M;
+    memset(&M, 0, sizeof(M));
+    if (carry_hist) {
+        M.it_hist = it_hist;
+        M.acc_hist = hist;
+    }
+    if (carry_sum) {
+        M.it_sum = it_sum;
+        M.acc_sum = sum;
+    }
     WhileCond wc;
     memset(&wc, 0, sizeof(wc));
     wc.channel = L.wcond.channel;
     wc.cmp = L.wcond.cmp;
     wc.threshold = L.wcond.threshold;
     wc.max = L.while_max;
-    const int every = L.wcond.check_every > 0 ? L.wcond.check_every : 8;
+    wc.kind = L.wcond.kind;
+    const bool async = L.wcond.check_every < 0;
+    const int every = async ? L.while_max : (L.wcond.check_every > 0 ? L.wcond.check_every : 8);
     HIP_TRY(launch_while_init(p->wstate, s));
     int it = 0;
     for (int block = 0; it < L.while_max; ++block) {
@@ -209,8 +234,8 @@ skel_status run_image_while(skel_plan p, const skel_buffer* args, hipStream_t s)
                 A.guard = p->wstate;
                 if (k.reduce) {
                     A.part = p->hrows;
-                    A.hist = hist;
-                    A.sum = sum;
+                    A.hist = it_hist;
+                    A.sum = it_sum;
                 }
                 HIP_TRY(launch_img_group(A, k.blur, k.reduce, k.wg, p->cfg.variant, s, &k.name));
                 if (k.reduce) {
@@ -218,8 +243,8 @@ skel_status run_image_while(skel_plan p, const skel_buffer* args, hipStream_t s)
                     memset(&F, 0, sizeof(F));
                     F.part = p->hrows;
                     F.guard = p->wstate;
-                    F.one.hist = hist;
-                    F.one.sum = sum;
+                    F.one.hist = it_hist;
+                    F.one.sum = it_sum;
                     F.one.nrows = k.grid;
                     F.one.crows = hist_chunk_rows(k.bins);
                     F.nseg = 1;
@@ -228,9 +253,9 @@ skel_status run_image_while(skel_plan p, const skel_buffer* args, hipStream_t s)
                     HIP_TRY(A.ntiles > 0 ? launch_hist_merge(F, s) : launch_hist_zero(F, s));
                 }
             }
-            HIP_TRY(launch_while_step(p->wstate, sum, wc, count, s));
+            HIP_TRY(launch_while_step(p->wstate, it_sum, wc, M, count, s));
         }
-        if (it >= L.while_max) break;
+        if (it >= L.while_max || async) break;
         HIP_TRY(hipMemcpyAsync(p->h_flag + block % 2, p->wstate, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
         HIP_TRY(hipEventRecord(p->wev[block % 2], s));
         if (block > 0) {
@@ -410,6 +435,8 @@ skel_status ensure_resources(skel_plan p) {
     if (p->lin.dom == DOM_U8 && p->lin.is_while && !p->wstate) {
         HIP_TRY(hipMalloc(&p->wbuf, std::max<size_t>(bytes, 16)));
         HIP_TRY(hipMalloc(&p->wstate, 256));
+        HIP_TRY(hipMalloc(&p->witer_hist, sizeof(uint32_t) * 1024 + sizeof(uint64_t) * 4));
+        p->witer_sum = reinterpret_cast<uint64_t*>(p->witer_hist + 1024);
         HIP_TRY(hipHostMalloc((void**)&p->h_flag, 256, hipHostMallocDefault));
         for (hipEvent_t& e : p->wev) HIP_TRY(hipEventCreateWithFlags(&e, hipEventDisableTiming));
     }
@@ -590,7 +617,16 @@ skel_status skel_loop_while(skel_node body, const skel_loop_state* ls, const ske
     if (body->kind != NK_MAPRED) return set_error(SKEL_EINVAL, "a while Loop's body must be a MapReduce");
     if (cond->channel < 0 || cond->channel > 3) return set_error(SKEL_EINVAL, "condition channel must be 0..3");
     if (cond->cmp < SKEL_CMP_GT || cond->cmp > SKEL_CMP_LE) return set_error(SKEL_EINVAL, "unknown comparison");
-    if (cond->check_every < 0) return set_error(SKEL_EINVAL, "negative check interval");
+    if (cond->kind != SKEL_COND_VALUE && cond->kind != SKEL_COND_DELTA)
+        return set_error(SKEL_EINVAL, "unknown condition kind %d", cond->kind);
+    // Plan arguments: in, out, [hist,] sum, count.  The images are carried by
+    // construction; reduce outputs may be; the count may not.
+    const int nargs = body->red == SKEL_RED_HIST256_SUM ? 5 : 4;
+    if (ls->carried_mask >> nargs)
+        return set_error(SKEL_EINVAL, "carried_mask 0x%x names arguments beyond the %d of this while Loop",
+                         ls->carried_mask, nargs);
+    if ((ls->carried_mask >> (nargs - 1)) & 1u)
+        return set_error(SKEL_EINVAL, "a while Loop's iteration count cannot be carried");
     skel_node_s* n;
     skel_status st = new_node(out, &n);
     if (st) return st;
@@ -694,9 +730,11 @@ skel_status skel_plan_describe(skel_plan p, char* buf, size_t len) {
     s += tmp;
     if (p->lin.is_while)
         snprintf(tmp, sizeof(tmp),
-                 ",\"while\":{\"max\":%d,\"channel\":%d,\"cmp\":%d,\"threshold\":%llu,\"check_every\":%d}",
+                 ",\"while\":{\"max\":%d,\"channel\":%d,\"cmp\":%d,\"threshold\":%llu,\"check_every\":%d,"
+                 "\"kind\":\"%s\"}",
                  p->lin.while_max, p->lin.wcond.channel, p->lin.wcond.cmp,
-                 (unsigned long long)p->lin.wcond.threshold, p->lin.wcond.check_every);
+                 (unsigned long long)p->lin.wcond.threshold, p->lin.wcond.check_every,
+                 p->lin.wcond.kind == SKEL_COND_DELTA ? "delta" : "value");
     else
         snprintf(tmp, sizeof(tmp), ",\"while\":null");
     s += tmp;
@@ -745,6 +783,7 @@ skel_status skel_plan_destroy(skel_plan p) {
     if (p->hrows) (void)hipFree(p->hrows);
     if (p->wbuf) (void)hipFree(p->wbuf);
     if (p->wstate) (void)hipFree(p->wstate);
+    if (p->witer_hist) (void)hipFree(p->witer_hist);
     if (p->h_flag) (void)hipHostFree(p->h_flag);
     for (hipEvent_t e : p->wev)
         if (e) (void)hipEventDestroy(e);

@@ -132,7 +132,9 @@ struct skel_plan_s {
     float2* fft_tw = nullptr;       // FFT roots of unity
     uint32_t* hrows = nullptr;      // image reduce: histogram rows, one per work-group
     void* wbuf = nullptr;           // while Loop: second image of the iteration ping-pong
-    uint32_t* wstate = nullptr;     // while Loop: device {continue flag, iterations run}
+    uint32_t* wstate = nullptr;     // while Loop: device {continue flag, iterations run, previous sum}
+    uint32_t* witer_hist = nullptr; // while Loop: one iteration's hist [4][256] when hist is carried ...
+    uint64_t* witer_sum = nullptr;  // ... and sums [4] when sum is carried (same allocation)
     uint32_t* h_flag = nullptr;     // while Loop: pinned host copies of the flag, one per block in flight
     hipEvent_t wev[2] = {nullptr, nullptr};  // while Loop: completion of those copies
     float4* nb_acc = nullptr;

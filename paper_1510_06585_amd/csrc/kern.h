@@ -99,18 +99,29 @@ hipError_t launch_hist_merge(const HistFinArgs& a, hipStream_t s);
 hipError_t launch_hist_zero(const HistFinArgs& a, hipStream_t s);
 
 // While Loop on the device.  state[0] = 1 while the loop runs, state[1] =
-// iterations run.  init sets {1, 0}; step (after each iteration's merge) counts
-// the iteration, stores the count to *count_out and clears the flag when
-// count == max or the condition on sum[channel] fails; copy moves `bytes`
-// from src to dst when max - count is odd (the last iteration wrote src).
+// iterations run, state[2..3] = the previous iteration's tested channel sum
+// (uint64).  init sets {1, 0}; step (after each iteration's merge) merges the
+// iteration's carried reduce outputs into their accumulators, counts the
+// iteration, stores the count to *count_out and clears the flag when
+// count == max or the condition fails (kind 0: sum[channel] cmp threshold;
+// kind 1: |sum[channel] - previous| cmp threshold, always true after the
+// first iteration); copy moves `bytes` from src to dst when max - count is
+// odd (the last iteration wrote src).
 struct WhileCond {
     int32_t channel, cmp;
     uint64_t threshold;
-    int32_t max, pad;
+    int32_t max, kind;
+};
+// Carried reduce outputs: acc += the iteration's result (null: not carried).
+struct WhileMerge {
+    const uint32_t* it_hist;
+    uint32_t* acc_hist;     // [4][256]
+    const uint64_t* it_sum;
+    uint64_t* acc_sum;      // [4]
 };
 hipError_t launch_while_init(uint32_t* state, hipStream_t s);
-hipError_t launch_while_step(uint32_t* state, const uint64_t* sum, const WhileCond& c, uint32_t* count_out,
-                             hipStream_t s);
+hipError_t launch_while_step(uint32_t* state, const uint64_t* sum, const WhileCond& c, const WhileMerge& m,
+                             uint32_t* count_out, hipStream_t s);
 hipError_t launch_while_copy(const uint32_t* state, const void* src, void* dst, uint64_t bytes, uint32_t max,
                              hipStream_t s);
 

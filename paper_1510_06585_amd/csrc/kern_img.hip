@@ -671,18 +671,38 @@ __global__ void while_init_kernel(uint32_t* st) {
     }
 }
 
-__global__ void while_step_kernel(uint32_t* st, const uint64_t* sum, const WhileCond c, uint32_t* count_out) {
-    if (threadIdx.x != 0 || st[0] == 0u) return;
+// One work-group of kStepThreads threads.  Every thread reads the flag before
+// thread 0 may clear it, so a finished loop merges nothing and a running one
+// merges the whole histogram.
+constexpr int kStepThreads = 256;
+__global__ void __launch_bounds__(kStepThreads) while_step_kernel(uint32_t* st, const uint64_t* sum,
+                                                                 const WhileCond c, const WhileMerge M,
+                                                                 uint32_t* count_out) {
+    const uint32_t running = st[0];
+    __syncthreads();
+    if (running == 0u) return;
+    if (M.acc_hist)
+        for (int b = threadIdx.x; b < 1024; b += kStepThreads) M.acc_hist[b] += M.it_hist[b];
+    if (M.acc_sum && threadIdx.x < 4) M.acc_sum[threadIdx.x] += M.it_sum[threadIdx.x];
+    if (threadIdx.x != 0) return;
     const uint32_t n = st[1] + 1u;
     st[1] = n;
     *count_out = n;
-    const uint64_t v = sum[c.channel];
-    bool go;
-    switch (c.cmp) {
-        case 0: go = v > c.threshold; break;
-        case 1: go = v >= c.threshold; break;
-        case 2: go = v < c.threshold; break;
-        default: go = v <= c.threshold; break;
+    uint64_t* prev = reinterpret_cast<uint64_t*>(st + 2);
+    const uint64_t s = sum[c.channel];
+    bool go = true;
+    uint64_t v = s;
+    if (c.kind == 1) {
+        v = s >= *prev ? s - *prev : *prev - s;
+        *prev = s;
+    }
+    if (c.kind == 0 || n > 1u) {
+        switch (c.cmp) {
+            case 0: go = v > c.threshold; break;
+            case 1: go = v >= c.threshold; break;
+            case 2: go = v < c.threshold; break;
+            default: go = v <= c.threshold; break;
+        }
     }
     if (!go || n >= (uint32_t)c.max) st[0] = 0u;
 }
@@ -848,10 +868,11 @@ hipError_t launch_while_init(uint32_t* state, hipStream_t s) {
     return hipGetLastError();
 }
 
-hipError_t launch_while_step(uint32_t* state, const uint64_t* sum, const WhileCond& c, uint32_t* count_out,
-                             hipStream_t s) {
-    if (c.channel < 0 || c.channel > 3) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(while_step_kernel, dim3(1), dim3(64), 0, s, state, sum, c, count_out);
+hipError_t launch_while_step(uint32_t* state, const uint64_t* sum, const WhileCond& c, const WhileMerge& m,
+                             uint32_t* count_out, hipStream_t s) {
+    if (c.channel < 0 || c.channel > 3 || c.kind < 0 || c.kind > 1) return hipErrorInvalidValue;
+    if (!m.acc_hist != !m.it_hist || !m.acc_sum != !m.it_sum) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(while_step_kernel, dim3(1), dim3(kStepThreads), 0, s, state, sum, c, m, count_out);
     return hipGetLastError();
 }
 

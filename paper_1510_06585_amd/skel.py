@@ -25,6 +25,8 @@ FUSE_AUTO, FUSE_OFF, FUSE_ON, FUSE_MASK = -1, 0, 1, 2
 IMMUTABLE, COPY = 1, 2
 CMP_GT, CMP_GE, CMP_LT, CMP_LE = range(4)
 CMP_BY_NAME = {">": CMP_GT, ">=": CMP_GE, "<": CMP_LT, "<=": CMP_LE}
+COND_VALUE, COND_DELTA = 0, 1
+COND_BY_NAME = {"value": COND_VALUE, "delta": COND_DELTA}
 
 OP_BY_NAME = {"noise": OP_NOISE, "solarise": OP_SOLARISE, "mirror": OP_MIRROR, "blur5": OP_BLUR5,
               "saxpy": OP_SAXPY, "nbody_force": OP_NBODY_FORCE, "leapfrog": OP_LEAPFROG, "fft": OP_FFT,
@@ -57,7 +59,7 @@ class LoopState(ctypes.Structure):
 
 class LoopCond(ctypes.Structure):
     _fields_ = [("channel", ctypes.c_int32), ("cmp", ctypes.c_int32), ("threshold", ctypes.c_uint64),
-                ("check_every", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("check_every", ctypes.c_int32), ("kind", ctypes.c_int32)]
 
 
 class PlanOpts(ctypes.Structure):
@@ -102,6 +104,10 @@ _SIGS = {
                                           ctypes.c_int32, ctypes.c_double, ctypes.c_double,
                                           ctypes.POINTER(PlanOpts), ctypes.POINTER(ctypes.c_double),
                                           ctypes.POINTER(ctypes.c_int32)]),
+    "skel_tune_batch": (ctypes.c_int32, [_node_p, ctypes.POINTER(Buffer), ctypes.c_int32, ctypes.c_int32,
+                                         ctypes.c_char_p, ctypes.c_int32, ctypes.c_int32, ctypes.c_double,
+                                         ctypes.POINTER(PlanOpts), ctypes.POINTER(ctypes.c_double),
+                                         ctypes.POINTER(ctypes.c_int32)]),
     "skel_config_count": (ctypes.c_int32, [_node_p, ctypes.POINTER(Buffer), ctypes.c_int32,
                                            ctypes.POINTER(ctypes.c_int32)]),
     "skel_feature_count": (ctypes.c_int32, []),
@@ -279,12 +285,16 @@ def Loop(body: Node, iterations: int, carried_mask: int = 0, global_sync: int = 
 
 
 def LoopWhile(body: Node, max_iterations: int, channel: int, cmp, threshold: int, check_every: int = 0,
-              carried_mask: int = 0, global_sync: int = 0) -> Node:
+              carried_mask: int = 0, global_sync: int = 0, kind="value") -> Node:
     """While Loop over an image MapReduce body: repeat while sum[channel] <cmp>
-    threshold (cmp: CMP_* or one of ">", ">=", "<", "<="), at most
-    max_iterations times; the condition is evaluated on the device."""
+    threshold (kind "value") or |sum[channel] - previous sum[channel]| <cmp>
+    threshold (kind "delta"), cmp: CMP_* or one of ">", ">=", "<", "<=", at
+    most max_iterations times; the condition is evaluated on the device.
+    check_every < 0 makes runs fully asynchronous; carried_mask bits on the
+    reduce outputs merge them by addition across iterations."""
     st = LoopState(max_iterations, carried_mask, global_sync)
-    c = LoopCond(channel, CMP_BY_NAME.get(cmp, cmp), threshold, check_every, 0)
+    k = COND_BY_NAME.get(kind, kind)
+    c = LoopCond(channel, CMP_BY_NAME.get(cmp, cmp), threshold, check_every, k)
     h = _node_p()
     _check(lib().skel_loop_while(body.handle, ctypes.byref(st), ctypes.byref(c), ctypes.byref(h)))
     return Node(h.value)
@@ -383,6 +393,22 @@ def tune(root: Node, args, db_path: str | None = None, reps: int = 10, max_confi
     _check(lib().skel_tune(root.handle, arr, n, db_path.encode() if db_path else None, reps, max_configs,
                            sample_seed, ctypes.byref(best), ctypes.byref(us)))
     return best.as_dict(), us.value
+
+
+def tune_batch(root: Node, reqs, db_path: str | None = None, reps: int = 10, pruned: bool = False,
+               precision_us: float = 0.0):
+    """Tunes tile height and work-group size of a batched run of `reqs` (a list
+    of per-request argument lists, or a BoundBatch) with skel_tune_batch;
+    returns (options, median us, number of points timed)."""
+    if not isinstance(reqs, BoundBatch):
+        reqs = BoundBatch(reqs)
+    best = PlanOpts()
+    us = ctypes.c_double()
+    timed = ctypes.c_int32()
+    _check(lib().skel_tune_batch(root.handle, reqs.arr, reqs.per, reqs.nreq,
+                                 db_path.encode() if db_path else None, reps, 1 if pruned else 0, precision_us,
+                                 ctypes.byref(best), ctypes.byref(us), ctypes.byref(timed)))
+    return best.as_dict(), us.value, timed.value
 
 
 def tune_pruned(root: Node, args, db_path: str | None = None, reps: int = 10, precision_us: float = 0.0,

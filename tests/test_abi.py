@@ -307,3 +307,19 @@ def test_batch_rejects_overlapping_requests():
     with pytest.raises(sk.SkelError) as e:
         p.batch_run([a], stream=0)
     assert e.value.status == sk.EINVAL
+
+
+def test_while_loop_option_rejections():
+    """Condition kind and carried_mask are checked when the node is built."""
+    body = sk.image_chain([("blur5", {})], "hist_sum")
+    body_sum = sk.image_chain([("blur5", {})], "sum")
+    for kw in ({"kind": 2}, {"carried_mask": 1 << 4}, {"carried_mask": 1 << 5}):
+        with pytest.raises(sk.SkelError) as e:
+            sk.LoopWhile(body, 3, 0, ">", 0, **kw)
+        assert e.value.status == sk.EINVAL, kw
+    with pytest.raises(sk.SkelError):
+        sk.LoopWhile(body_sum, 3, 0, ">", 0, carried_mask=1 << 3)      # the count of a SUM body
+    # accepted: images (always carried), reduce outputs, both kinds, asynchronous runs
+    for kw in ({"carried_mask": 0b1111}, {"kind": "delta", "check_every": -1}):
+        sk.LoopWhile(body, 3, 0, ">", 0, **kw)
+    sk.LoopWhile(body_sum, 3, 0, ">", 0, carried_mask=0b111)
