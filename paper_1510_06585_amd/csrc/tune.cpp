@@ -512,3 +512,168 @@ extern "C" skel_status skel_tune_pruned(skel_node root, const skel_buffer* args,
     if (timed) *timed = ntimed;
     return SKEL_OK;
 }
+
+// Auto Tuner for batched runs (Sec. 2.2, applied to the batch execution
+// model of Sec. 2).  The persistent batched kernel runs the fully fused plan
+// (one kernel: the only partition a single persistent launch can hold), so the
+// search is over the tile height every request is cut into and the
+// work-group size (= wavefronts, hence adjacent tiles, per group), each point
+// timed as a whole skel_batch_run of the caller's request set: 3 warm-up runs
+// (the first lays out the work list and captures the graph), then the median
+// of `reps` runs.  Exhaustive: every point.  pruned != 0: Algorithm 1's
+// ordered walk -- work-group sizes in non-increasing order of resident
+// wavefronts, the first size that does not improve ends the search; per size,
+// tile heights increase while each improves by at least precision_us.
+namespace {
+
+constexpr int kBatchTileCands[] = {8, 12, 16, 24, 31, 40, 48, 64, 96, 128};
+constexpr int kBatchWgCands[] = {64, 128, 256};
+
+}  // namespace
+
+extern "C" skel_status skel_tune_batch(skel_node root, const skel_buffer* args, int32_t nargs, int32_t nreq,
+                                       const char* db_path, int32_t reps, int32_t pruned, double precision_us,
+                                       skel_plan_opts* best, double* best_us, int32_t* timed) {
+    clear_error();
+    if (!root || !best || !args || nreq < 1) return set_error(SKEL_EINVAL, "null root, result or empty request set");
+    Linear L;
+    Shape sh;
+    skel_status st = linearize(root, L);
+    if (!st && L.dom == DOM_NONE) L.dom = (nargs > 0 && args[0].dtype == SKEL_U8) ? DOM_U8 : DOM_F32;
+    if (!st) st = derive_shape(L, args, nargs, sh);
+    if (st) return st;
+    if (L.dom != DOM_U8 || L.is_while) return set_error(SKEL_EUNSUPPORTED, "batched runs are image chains");
+    if (reps <= 0) reps = 10;
+    if (precision_us < 0) precision_us = 0;
+    // The knowledge-base row describes the whole batch: the key names the
+    // request count and total pixels, the features a square image of the
+    // batch's total pixel count.
+    double px = 0;
+    for (int r = 0; r < nreq; ++r) px += (double)args[(size_t)r * nargs].shape[0] * args[(size_t)r * nargs].shape[1];
+    Shape tot;
+    tot.W = tot.H = std::max<int64_t>(1, (int64_t)std::llround(std::sqrt(px)));
+    char kb[64];
+    snprintf(kb, sizeof(kb), "batch%d|px%.0f|", nreq, px);
+    const std::string key = kb + composition_key(L, sh);
+
+    struct Cand {
+        int wg, th, occ;
+    };
+    std::vector<std::vector<Cand>> by_wg;   // per work-group size, increasing tile height
+    for (int wg : kBatchWgCands) {
+        std::vector<Cand> v;
+        for (int th : kBatchTileCands) v.push_back(Cand{wg, th, 0});
+        by_wg.push_back(v);
+    }
+    if (pruned) {
+        // resident wavefronts per CU of the fused kernel at each size (the
+        // batched kernel shares its register and LDS footprint)
+        skel_plan_opts d;
+        skel_plan_opts_default(&d);
+        for (auto& v : by_wg) {
+            d.wg = v[0].wg;
+            d.tile_h = v[0].th;
+            Config c;
+            std::vector<Kernel> ks;
+            int occ = 0;
+            if (!resolve_config(L, sh, &d, c) && !build_kernels(L, sh, c, ks) && ks.size() == 1)
+                occ = img_waves_per_cu(ks[0].img, ks[0].blur, ks[0].reduce, ks[0].wg, c.variant);
+            for (Cand& x : v) x.occ = occ;
+        }
+        std::stable_sort(by_wg.begin(), by_wg.end(),
+                         [](const std::vector<Cand>& a, const std::vector<Cand>& b) { return a[0].occ > b[0].occ; });
+    }
+
+    FILE* db = nullptr;
+    if (db_path && *db_path) {
+        db = fopen(db_path, "a");
+        if (!db) return set_error(SKEL_EINVAL, "cannot open %s", db_path);
+    }
+    if (db) db_session(db, pruned ? "batch-pruned" : "batch-exhaustive", key);
+    Timer T;
+    if ((st = T.init())) {
+        if (db) fclose(db);
+        return st;
+    }
+    double best_t = 1e300;
+    Config best_c;
+    bool have = false;
+    int ntimed = 0;
+    skel_status result = SKEL_OK;
+    auto time_one = [&](const Cand& x, double* med, double* mn) -> skel_status {
+        skel_plan_opts o;
+        skel_plan_opts_default(&o);
+        o.fusion = SKEL_FUSE_ON;
+        o.tile_h = x.th;
+        o.wg = x.wg;
+        skel_plan p = nullptr;
+        if (skel_plan_compile(root, args, nargs, &o, &p)) return SKEL_EINVAL;
+        if (p->kernels.size() != 1) {
+            skel_plan_destroy(p);
+            return SKEL_EINVAL;
+        }
+        skel_status s2 = SKEL_OK;
+        for (int w = 0; w < 3 && !s2; ++w) s2 = skel_batch_run(p, args, nargs, nreq, T.s);
+        T.times.clear();
+        hipError_t e = hipSuccess;
+        for (int r = 0; r < reps && !s2 && e == hipSuccess; ++r) {
+            e = hipEventRecord(T.e0, T.s);
+            if (e != hipSuccess) break;
+            s2 = skel_batch_run(p, args, nargs, nreq, T.s);
+            if (s2) break;
+            float ms = 0;
+            e = hipEventRecord(T.e1, T.s);
+            if (e == hipSuccess) e = hipEventSynchronize(T.e1);
+            if (e == hipSuccess) e = hipEventElapsedTime(&ms, T.e0, T.e1);
+            if (e == hipSuccess) T.times.push_back(ms * 1000.0f);
+        }
+        const hipError_t es = hipStreamSynchronize(T.s);
+        if (e == hipSuccess) e = es;
+        skel_plan_destroy(p);
+        if (s2) return s2 == SKEL_EINVAL ? SKEL_EDEVICE : s2;
+        if (e != hipSuccess) return set_error(SKEL_EDEVICE, "timing a batch candidate: %s", hipGetErrorString(e));
+        if (T.times.empty()) return set_error(SKEL_EINVAL, "no timed repetitions");
+        std::sort(T.times.begin(), T.times.end());
+        *med = T.times[T.times.size() / 2];
+        *mn = T.times.front();
+        return SKEL_OK;
+    };
+    for (const auto& v : by_wg) {
+        const double before = best_t;
+        for (const Cand& x : v) {
+            double med = 0, mn = 0;
+            st = time_one(x, &med, &mn);
+            if (st == SKEL_EINVAL) continue;
+            if (st) {
+                result = st;
+                break;
+            }
+            ++ntimed;
+            Config c;
+            c.fusion = SKEL_FUSE_ON;
+            c.tile_h = x.th;
+            c.wg = x.wg;
+            if (db) db_row(db, key, L, tot, c, med, mn);
+            const bool better = med < best_t;
+            const double gain = best_t - med;
+            if (better) {
+                best_t = med;
+                best_c = c;
+                have = true;
+            }
+            if (pruned && (!better || gain < precision_us)) break;
+        }
+        if (result) break;
+        if (pruned && have && !(best_t < before)) break;
+    }
+    if (db) fclose(db);
+    if (result) return result;
+    if (!have) return set_error(SKEL_EUNSUPPORTED, "no batch configuration could be timed");
+    skel_plan_opts_default(best);
+    best->fusion = SKEL_FUSE_ON;
+    best->tile_h = best_c.tile_h;
+    best->wg = best_c.wg;
+    if (best_us) *best_us = best_t;
+    if (timed) *timed = ntimed;
+    return SKEL_OK;
+}

@@ -100,3 +100,39 @@ def test_batch_needs_a_fused_plan():
     with pytest.raises(sk.SkelError) as e:
         p.batch_run(reqs)
     assert e.value.status == sk.EUNSUPPORTED
+
+
+def test_batch_tuner_choice_matches_oracle(tmp_path):
+    """skel_tune_batch on an uneven batch: the exhaustive search times all 30
+    points (10 tile heights x 3 work-group sizes) and logs each after one
+    provenance line; the Algorithm-1 walk times a subset of them; the batched
+    run with either choice equals the oracle for every request."""
+    rng = np.random.default_rng(23)
+    sides = [(int(s), int(s)) for s in np.round(64 * 16 ** rng.random(24))]
+    sides[3] = (37, 1001)
+    reqs, imgs = make_reqs(sides, 7000)
+    root = sk.image_chain(PIPE_NSBM, "hist_sum")
+    db = str(tmp_path / "batch.db")
+    best, us, timed = sk.tune_batch(root, reqs, db, reps=5)
+    assert timed == 30 and us > 0
+    lines = open(db).read().splitlines()
+    assert lines[0].startswith("# skel tuning session: tuner=batch-exhaustive")
+    rows = [l for l in lines if not l.startswith("#")]
+    assert len(rows) == 30 and all(r.startswith("batch24|px") for r in rows)
+    assert min(float(r.split(",")[-2]) for r in rows) == pytest.approx(us, rel=1e-3)
+    best_p, us_p, timed_p = sk.tune_batch(root, reqs, db, reps=5, pruned=True, precision_us=1.0)
+    assert 1 <= timed_p < 30
+    for opt in (best, best_p):
+        assert opt["fusion"] == sk.FUSE_ON and opt["wg"] in (64, 128, 256)
+        p = plan_for(PIPE_NSBM, options={"tile_h": opt["tile_h"], "wg": opt["wg"]})
+        for a in reqs:
+            a[1].fill_(3)
+            a[2].fill_(3)
+        p.batch_run(reqs)
+        torch.cuda.synchronize()
+        for (H, W), img, a in zip(sides, imgs, reqs):
+            ref, rh, rs = oracle.run_image_pipeline(img, PIPE_NSBM, "hist_sum")
+            assert_image_equal(a[1].cpu().numpy(), ref, f"{H}x{W} tuned {opt}")
+            assert (a[2].cpu().numpy().view(np.uint32) == rh).all()
+            assert (a[3].cpu().numpy().view(np.uint64) == rs).all()
+        p.destroy()
