@@ -329,8 +329,18 @@ def bench_batch():
     root = sk.image_chain(PIPE_NSBM, "hist_sum")
     proto = [sk.proto([8, 8, 4], sk.U8)] * 2 + [sk.proto([4, 256], sk.U32), sk.proto([4], sk.U64)]
     res = {"requests": 256, "pixels": px}
-    bp = sk.Plan(root, proto)
     bound = sk.bind_batch(reqs)      # marshal the 1024 buffers once, as a serving loop would
+    # tile height and work-group size of the persistent launch chosen by the
+    # batch autotuner (exhaustive over its 30 points; untimed here)
+    t0 = time.perf_counter()
+    best, tuned_us, ntimed = sk.tune_batch(root, bound, None, reps=10)
+    res["autotune"] = {"tile_h": best["tile_h"], "wg": best["wg"], "points_timed": ntimed,
+                       "median_us": round(tuned_us, 2), "seconds": round(time.perf_counter() - t0, 2)}
+    bp_default = sk.Plan(root, proto)
+    _, ms = timed_runs(lambda: bp_default.batch_run(bound), 30, 5)
+    res["default_plan_ms"] = round(ms / 30, 4)
+    bp_default.destroy()
+    bp = sk.Plan(root, proto, {"tile_h": best["tile_h"], "wg": best["wg"]})
     _, ms = timed_runs(lambda: bp.batch_run(bound), 30, 5)
     ms /= 30
     res["batched_ms"] = round(ms, 4)
@@ -378,6 +388,14 @@ def bench_while():
     res["device_condition_ms_per_iteration"] = round(ms / 10 / iters, 5)
     assert int(count.cpu().numpy().view(np.uint32)[0]) == iters
     wplan.destroy()
+    # asynchronous runs (no host read-back), the convergence form of the
+    # condition and both reduce outputs carried (merged by addition)
+    aplan = sk.Plan(sk.LoopWhile(body, iters, 0, ">=", 0, -1, carried_mask=0b1100, kind="delta"),
+                    [x, y, hist, sums, count])
+    _, ms = timed_runs(lambda: aplan.run(wb), 10, 3)
+    res["async_delta_carried_ms_per_iteration"] = round(ms / 10 / iters, 5)
+    assert int(count.cpu().numpy().view(np.uint32)[0]) == iters
+    aplan.destroy()
     bplan = sk.Plan(body, [x, y, hist, sums])
     a, b2 = sk.bind([x, y, hist, sums]), sk.bind([y, x, hist, sums])
 
@@ -502,6 +520,27 @@ def bench_segment():
     return res
 
 
+def bench_selector(n_train, n_test):
+    """The learned-selector experiment (cost-model MLP trained on the GPU on
+    autotuner-measured runtimes, scored on held-out compositions against their
+    exhaustive best), with the labels' re-timing noise floor."""
+    import shutil
+    import tempfile
+    from paper_1510_06585_amd import selector
+    wd = tempfile.mkdtemp(prefix="skel_selector_")
+    t0 = time.perf_counter()
+    try:
+        r = selector.experiment(n_train=n_train, n_test=n_test, workdir=wd, log=log)
+    finally:
+        shutil.rmtree(wd, ignore_errors=True)
+    r.pop("workdir", None)
+    r["seconds"] = round(time.perf_counter() - t0, 1)
+    r["target"] = {"mean_regret_le": 0.10, "met": r["regret"]["model"]["mean"] <= 0.10,
+                   "label_noise_median_lt": 0.03,
+                   "label_noise_met": bool(r["label_noise"] and r["label_noise"]["rel_diff"]["median"] < 0.03)}
+    return r
+
+
 def profile_run(steps):
     """Short run for hardware-counter passes: the fused 8192^2 Pipeline+MapReduce kernel and a
     plain copy of the same image (the byte-count reference), `steps` each."""
@@ -559,6 +598,7 @@ def main():
     ap.add_argument("--while-only", action="store_true",
                     help="only the 8192x8192 x 10 while Loop against its host-checked and unchecked forms "
                          "(for a kernel trace)")
+    ap.add_argument("--no-selector", action="store_true", help="leave the learned-selector experiment out of the extras")
     ap.add_argument("--selector-dir", default=None, help="where the selector experiment keeps its databases")
     ap.add_argument("--selector-train", type=int, default=1000)
     ap.add_argument("--selector-test", type=int, default=200)
@@ -609,6 +649,9 @@ def main():
         extras["saxpy_5e7"] = bench_saxpy()
         log("Segmentation: 60 MiB gray volume, one stage and a 3-stage chain")
         extras["segment_60MiB"] = bench_segment()
+        if not a.no_selector:
+            log("learned selector: 1000 training / 200 held-out compositions")
+            extras["selector"] = bench_selector(a.selector_train, a.selector_test)
         out["extras"] = extras
     if not a.no_cpu_baseline:
         log("cpu baseline: oracle on the host")

@@ -392,6 +392,16 @@ skel_status skel_tune_pruned(skel_node root, const skel_buffer* args, int32_t na
                              int32_t reps, double precision_us, double occ_threshold, skel_plan_opts* best,
                              double* best_us, int32_t* timed);
 
+/* Times one configuration of `root` over the given (device) arguments with
+ * the tuner's protocol (a fresh plan compiled with *opts -- NULL: defaults --,
+ * 3 warm-up runs, then `reps` runs each bracketed by HIP events on a private
+ * stream; reps <= 0: 10), so that a baseline or a re-timing compares with the
+ * tuning database's rows like for like.  Writes the median and (may be NULL)
+ * minimum in microseconds.  Synchronises the device; the arguments' contents
+ * are overwritten.  Compile errors are reported as by skel_plan_compile. */
+skel_status skel_time_config(skel_node root, const skel_buffer* args, int32_t nargs, const skel_plan_opts* opts,
+                             int32_t reps, double* median_us, double* min_us);
+
 /* Auto Tuner for batched runs (Sec. 2.2 applied to the batch execution
  * model of Sec. 2): times skel_batch_run of the request set args[r*nargs+k]
  * (nreq requests shaped as for skel_batch_run) over tile height x work-group

@@ -60,6 +60,16 @@ static __device__ __forceinline__ uint32_t odd_bytes(uint32_t v) {
     return __builtin_amdgcn_perm(0u, v, 0x0C030C01u);
 }
 
+// h ^ (h >> 16) as one SDWA instruction: the low half becomes lo ^ hi and
+// the high half is kept (it is xored with zero).
+static __device__ __forceinline__ uint32_t xor_hi_into_lo(uint32_t h) {
+    uint32_t r = h;
+    asm("v_xor_b32_sdwa %0, %1, %1 dst_sel:WORD_0 dst_unused:UNUSED_PRESERVE src0_sel:WORD_1 src1_sel:WORD_0"
+        : "+v"(r)
+        : "v"(h));
+    return r;
+}
+
 // The MurmurHash3 32-bit finaliser (written from its public description) of
 // the key seed ^ ((y << 16) | x), x < 2^16.  The key's high half does not
 // depend on x, so the finaliser's first xor-shift k ^ (k >> 16) equals
@@ -70,8 +80,7 @@ static __device__ __forceinline__ uint32_t px_hash(uint32_t seed, uint32_t x, ui
     h *= 0x85EBCA6Bu;
     h ^= h >> 13;
     h *= 0xC2B2AE35u;
-    h ^= h >> 16;
-    return h;
+    return xor_hi_into_lo(h);
 }
 
 static __device__ __forceinline__ void noise_px(uint32_t& e, uint32_t& o, uint32_t seed, uint32_t x,

@@ -52,6 +52,21 @@ std::vector<Config> enumerate_configs(const Linear& L, const Shape& sh) {
         }
     else
         masks.push_back(0);
+    std::vector<int> u8_tile_ladder;
+    if (L.dom == DOM_U8) {
+        Config fc = base;
+        fc.fusion = SKEL_FUSE_ON;
+        fc.wg = 256;
+        std::vector<Kernel> ks;
+        int f = std::max(2, base.tile_h);
+        if (!build_kernels(L, sh, fc, ks) && !ks.empty()) f = std::max(2, (int)ks[0].img.tile_h);
+        const int hmax = std::max<int>(2, (int)std::min<int64_t>(sh.H, kMaxDim));
+        for (int th : {f / 4, f / 2, f, 2 * f}) {
+            th = std::min(std::max(th, 2), hmax);
+            if (std::find(u8_tile_ladder.begin(), u8_tile_ladder.end(), th) == u8_tile_ladder.end())
+                u8_tile_ladder.push_back(th);
+        }
+    }
     for (uint32_t m : masks) {
         if (L.dom == DOM_GRAY) {
             for (int ept : {1, 8}) {
@@ -67,19 +82,23 @@ std::vector<Config> enumerate_configs(const Linear& L, const Shape& sh) {
             c.split_mask = m;
             if (config_valid(L, sh, c)) out.push_back(c);
         } else if (L.dom == DOM_U8) {
-            const int th0 = base.tile_h;
-            const int variants[3][2] = {{256, th0}, {64, std::max(8, th0 / 2)}, {256, std::min(1024, th0 * 2)}};
-            for (const auto& v : variants) {
-                Config c = base;
-                c.fusion = k >= 1 ? SKEL_FUSE_MASK : SKEL_FUSE_ON;
-                c.split_mask = m;
-                c.wg = v[0];
-                c.tile_h = v[1];
-                if (config_valid(L, sh, c)) out.push_back(c);
-            }
+            // Work-group sizes 64, 128, 256 x four explicit tile heights around
+            // the fitted default of the fully fused kernel (a quarter, a half,
+            // once and twice it, within [2, H]); explicit heights, so the
+            // features and the timed plan see the same tiles.
+            for (int wg : {64, 128, 256})
+                for (int th : u8_tile_ladder) {
+                    Config c = base;
+                    c.fusion = k >= 1 ? SKEL_FUSE_MASK : SKEL_FUSE_ON;
+                    c.split_mask = m;
+                    c.wg = wg;
+                    c.tile_h = th;
+                    c.auto_tile = false;
+                    if (config_valid(L, sh, c)) out.push_back(c);
+                }
         } else {
             for (int wg : {64, 256, 1024})
-                for (int ept : {1, 8}) {
+                for (int ept : {1, 2, 4, 8}) {
                     Config c = base;
                     c.fusion = k >= 1 ? SKEL_FUSE_MASK : SKEL_FUSE_ON;
                     c.split_mask = m;
@@ -242,6 +261,10 @@ struct Timer {
                      double* med, double* mn) {
         skel_plan_opts o;
         config_to_opts(c, &o);
+        return time_opts(root, args, nargs, o, reps, med, mn);
+    }
+    skel_status time_opts(skel_node root, const skel_buffer* args, int32_t nargs, const skel_plan_opts& o, int reps,
+                          double* med, double* mn) {
         skel_plan p = nullptr;
         skel_status st = skel_plan_compile(root, args, nargs, &o, &p);
         if (st) return SKEL_EINVAL;
@@ -359,6 +382,39 @@ extern "C" skel_status skel_tune(skel_node root, const skel_buffer* args, int32_
     if (result) return result;
     config_to_opts(best_c, best);
     if (best_us) *best_us = best_t;
+    return SKEL_OK;
+}
+
+// One configuration timed with the tuner's own protocol, so that baselines
+// and re-timings compare with its rows like for like.
+extern "C" skel_status skel_time_config(skel_node root, const skel_buffer* args, int32_t nargs,
+                                        const skel_plan_opts* opts, int32_t reps, double* median_us,
+                                        double* min_us) {
+    clear_error();
+    if (!root || !median_us) return set_error(SKEL_EINVAL, "null root or result");
+    Linear L;
+    Shape sh;
+    Config c;
+    skel_status st = linearize(root, L);
+    if (!st && L.dom == DOM_NONE) L.dom = (nargs > 0 && args[0].dtype == SKEL_U8) ? DOM_U8 : DOM_F32;
+    if (!st) st = derive_shape(L, args, nargs, sh);
+    if (!st) st = resolve_config(L, sh, opts, c);
+    if (st) return st;
+    if (reps <= 0) reps = 10;
+    skel_plan_opts o;
+    if (opts) o = *opts; else skel_plan_opts_default(&o);
+    Timer T;
+    if ((st = T.init())) return st;
+    double med = 0, mn = 0;
+    // Timer::time compiles from options; pass the caller's as given so that
+    // defaults (auto tile heights) stay defaults
+    skel_plan p = nullptr;
+    if ((st = skel_plan_compile(root, args, nargs, &o, &p))) return st;
+    skel_plan_destroy(p);
+    st = T.time_opts(root, args, nargs, o, reps, &med, &mn);
+    if (st) return st;
+    *median_us = med;
+    if (min_us) *min_us = mn;
     return SKEL_OK;
 }
 

@@ -169,8 +169,68 @@ def while_phases(path):
     return out
 
 
+COMMAND_DRIVER = ("rocprofv3 --kernel-trace --stats -d DIR -o driver --output-format csv -- python3 bench.py "
+                  "--gpus 1 --steps 20 --warmup 5")
+PLAIN_FIRST = "img_band_kernel<1, 0, false, false, 0>"   # noise alone: the plain plan's first kernel
+
+
+def driver_phase(dispatch_csv, steps):
+    """Durations (ns) of the fused 8192^2 kernel's dispatches in the headline
+    measurement of a default bench run: every dispatch of the fused kernel
+    before the plain plan's first kernel (warm-up, timed steps, then the
+    `steps` launches whose HIP events give roofline.kernel_ms, last)."""
+    rows = sorted(csv.DictReader(open(dispatch_csv)), key=lambda r: int(r["Start_Timestamp"]))
+    out = []
+    for r in rows:
+        if PLAIN_FIRST in r["Kernel_Name"]:
+            break
+        if FUSED in r["Kernel_Name"]:
+            out.append(int(r["End_Timestamp"]) - int(r["Start_Timestamp"]))
+    return out, out[-steps:]
+
+
+def driver_summary(stats_csv, dispatch_csv, bench_json):
+    import statistics
+    line = json.loads([ln for ln in open(bench_json) if ln.startswith("{")][-1])
+    steps = int(line["steps"])
+    allf, last = driver_phase(dispatch_csv, steps)
+    algo = line["roofline"]["algorithmic_bytes"]
+    mean = statistics.mean(last)
+    out = ["# rocprofv3 summary: the default bench command, fused Pipeline+MapReduce 8192x8192 RGBA u8 "
+           "(headline kernel) and every other kernel of the run", "",
+           "Command (repository root on the MI355X host, TMPDIR=/tmp):", "", "```", COMMAND_DRIVER, "```", "",
+           "## Headline kernel in this run", "",
+           f"The bench line printed under the profiler: value {line['value']} {line['unit']}, ms_per_step "
+           f"{line['ms_per_step']}, roofline.kernel_ms {line['roofline']['kernel_ms']} (HIP events around the "
+           f"last {steps} launches), frac {line['roofline']['frac']}.", "",
+           f"From the per-dispatch trace, the fused kernel `{FUSED}` ran {len(allf)} times before the plain plan "
+           f"started (the untimed warm-up floor, the {steps} timed steps, then the {steps} launches the HIP "
+           "events bracket):", "",
+           "| dispatches | mean us | median us | min us | max us | frac of 8 TB/s (algorithmic bytes / mean) |",
+           "|---|---|---|---|---|---|",
+           f"| last {steps} | {mean/1e3:.2f} | {statistics.median(last)/1e3:.2f} | {min(last)/1e3:.2f} | "
+           f"{max(last)/1e3:.2f} | {algo / (mean * 1e-9) / 1e9 / HBM_PEAK_GBS:.4f} |",
+           f"| first 20 (clock ramp) | {statistics.mean(allf[:20])/1e3:.2f} | {statistics.median(allf[:20])/1e3:.2f} "
+           f"| {min(allf[:20])/1e3:.2f} | {max(allf[:20])/1e3:.2f} | "
+           f"{algo / (statistics.mean(allf[:20]) * 1e-9) / 1e9 / HBM_PEAK_GBS:.4f} |",
+           f"| all {len(allf)} | {statistics.mean(allf)/1e3:.2f} | {statistics.median(allf)/1e3:.2f} | "
+           f"{min(allf)/1e3:.2f} | {max(allf)/1e3:.2f} | "
+           f"{algo / (statistics.mean(allf) * 1e-9) / 1e9 / HBM_PEAK_GBS:.4f} |", "",
+           f"Algorithmic bytes per launch: {algo} (image read and written once, 4 x 256 x 4 B histogram, 4 x 8 B "
+           "sums).", "",
+           "## Kernel statistics of the whole run (--stats; averages mix workloads where one kernel serves "
+           "several)", "", "| kernel | calls | avg us | min us | max us |", "|---|---|---|---|---|"]
+    for r in kernel_stats(stats_csv)[:25]:
+        out.append(f"| `{r['name'][:90]}` | {r['calls']} | {r['avg_ns']/1e3:.2f} | {r['min_ns']/1e3:.2f} | "
+                   f"{r['max_ns']/1e3:.2f} |")
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
+    ap.add_argument("--driver-stats", help="kernel stats of the default bench command under the profiler")
+    ap.add_argument("--driver-dispatches", help="the per-dispatch kernel trace of the same run")
+    ap.add_argument("--driver-json", help="the JSON line that run printed")
     ap.add_argument("--trace")
     ap.add_argument("--fetch")
     ap.add_argument("--write")
@@ -184,6 +244,9 @@ def main():
     ap.add_argument("--out", required=True)
     a = ap.parse_args()
     os.makedirs(a.out, exist_ok=True)
+    if a.driver_stats and a.driver_dispatches and a.driver_json:
+        d = driver_summary(a.driver_stats, a.driver_dispatches, a.driver_json)
+        open(os.path.join(a.out, "driver_command_8192.md"), "w").write("\n".join(d) + "\n")
     if a.trace_filter_pipeline:
         c1 = ["# rocprofv3 summary: filter pipeline 1024x1024 RGBA u8 (noise > solarise > mirror), plain plan "
               "(one kernel per stage) and fused plan, 220 runs each", "",

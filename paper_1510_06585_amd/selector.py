@@ -77,23 +77,12 @@ def _read_rows(path):
     return rows
 
 
-def _time_default(root, args, reps=10):
-    import torch
-    p = sk.Plan(root, args)
-    b = sk.bind(args)
-    for _ in range(3):
-        p.run(b)
-    torch.cuda.synchronize()
-    ts = []
-    for _ in range(reps):
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        e0.record()
-        p.run(b)
-        e1.record()
-        e1.synchronize()
-        ts.append(e0.elapsed_time(e1) * 1000.0)
-    p.destroy()
-    return float(np.median(ts))
+def _time_default(root, args, reps=10, opts=None):
+    """Median microseconds of the plan compiled with `opts` (None: the default
+    plan), timed by the library with the tuner's own protocol (3 warm-up
+    runs, `reps` runs bracketed by HIP events on a private stream), so that it
+    compares with the tuning database's rows like for like."""
+    return sk.time_config(root, args, opts, reps)[0]
 
 
 def _match(rows, opts):
@@ -105,6 +94,11 @@ def _match(rows, opts):
     return None
 
 
+def _opts_of(row):
+    f, m, th, wg, ept, var = row["cfg"]
+    return {"fusion": f, "split_mask": m, "tile_h": th, "wg": wg, "ept": ept, "variant": var}
+
+
 def _stats(reg):
     reg = np.asarray(reg, np.float64)
     return {"mean": round(float(reg.mean()), 4), "median": round(float(np.median(reg)), 4),
@@ -113,7 +107,11 @@ def _stats(reg):
 
 
 def experiment(n_train: int = 1000, n_test: int = 200, per_train: int = 20, seed: int = 5,
-               epochs: int = 200, workdir: str | None = None, log=print):
+               epochs: int = 200, workdir: str | None = None, log=print, noise_check: bool = True):
+    """Runs the experiment; with noise_check, every held-out composition's
+    best and runner-up configurations are re-timed twice more once its labels
+    and its pruned search are done (fresh plans, the same protocol: 3 warm-up
+    runs, median of 10), giving the labels' run-to-run noise floor."""
     import torch
     import synth
     rng = np.random.default_rng(seed)
@@ -146,7 +144,7 @@ def experiment(n_train: int = 1000, n_test: int = 200, per_train: int = 20, seed
             log(f"train {i}/{len(train)} {time.time() - t0:.0f}s")
     n_labels = len(_read_rows(train_db))
     t_train_labels = time.time() - t0
-    test_rows, defaults, pruned = [], [], []
+    test_rows, defaults, pruned, noise = [], [], [], []
     for i, c in enumerate(test):
         root = sk.image_chain(c["stages"], c["reduce"])
         args = _args_for(c, gen)
@@ -157,6 +155,16 @@ def experiment(n_train: int = 1000, n_test: int = 200, per_train: int = 20, seed
         defaults.append(_time_default(root, args))
         popts, _, ptimed = sk.tune_pruned(root, args, None, reps=10)
         pruned.append((popts, ptimed))
+        if noise_check and len(rows) >= 2:
+            # label noise floor: re-time the best and the runner-up twice
+            order = sorted(rows, key=lambda r: r["t"])
+            rb, ru = order[0], order[1]
+            tb = [_time_default(root, args, 10, _opts_of(rb)) for _ in range(2)]
+            tu = [_time_default(root, args, 10, _opts_of(ru)) for _ in range(2)]
+            noise.append({"best": [abs(t / rb["t"] - 1.0) for t in tb],
+                          "runner_up": [abs(t / ru["t"] - 1.0) for t in tu],
+                          "gap": ru["t"] / rb["t"] - 1.0,
+                          "order_kept": float(np.mean(tb) <= np.mean(tu))})
         del args
         if i % 20 == 0:
             log(f"test {i}/{len(test)} {time.time() - t0:.0f}s")
@@ -209,8 +217,20 @@ def experiment(n_train: int = 1000, n_test: int = 200, per_train: int = 20, seed
         reg["random"].append(rows[int(rng.integers(0, len(rows)))]["t"] / best - 1.0)
         t = _match(rows, popts)
         reg["pruned_tuner"].append((t if t is not None else tdef) / best - 1.0)
+    label_noise = None
+    if noise:
+        allrel = [x for n in noise for x in n["best"] + n["runner_up"]]
+        label_noise = {"retimed_configs": len(allrel),
+                       "rel_diff": _stats(allrel),
+                       "best": _stats([x for n in noise for x in n["best"]]),
+                       "runner_up": _stats([x for n in noise for x in n["runner_up"]]),
+                       "best_vs_runner_up_gap": _stats([n["gap"] for n in noise]),
+                       "order_kept_frac": round(float(np.mean([n["order_kept"] for n in noise])), 4),
+                       "note": "|re-timed / labelled - 1| of each held-out composition's best and runner-up "
+                               "configuration, two re-timings each (median of 10 runs after 3 warm-ups)"}
     return {
         "experiment": "learned config selector",
+        "label_noise": label_noise,
         "train_compositions": len(train), "heldout_compositions": len(test), "labels": n_labels,
         "heldout_configs_timed": int(sum(len(r) for r in test_rows)),
         "pruned_tuner_configs_timed": int(sum(t for _, t in pruned)),

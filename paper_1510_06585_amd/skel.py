@@ -104,6 +104,9 @@ _SIGS = {
                                           ctypes.c_int32, ctypes.c_double, ctypes.c_double,
                                           ctypes.POINTER(PlanOpts), ctypes.POINTER(ctypes.c_double),
                                           ctypes.POINTER(ctypes.c_int32)]),
+    "skel_time_config": (ctypes.c_int32, [_node_p, ctypes.POINTER(Buffer), ctypes.c_int32, ctypes.POINTER(PlanOpts),
+                                          ctypes.c_int32, ctypes.POINTER(ctypes.c_double),
+                                          ctypes.POINTER(ctypes.c_double)]),
     "skel_tune_batch": (ctypes.c_int32, [_node_p, ctypes.POINTER(Buffer), ctypes.c_int32, ctypes.c_int32,
                                          ctypes.c_char_p, ctypes.c_int32, ctypes.c_int32, ctypes.c_double,
                                          ctypes.POINTER(PlanOpts), ctypes.POINTER(ctypes.c_double),
@@ -393,6 +396,16 @@ def tune(root: Node, args, db_path: str | None = None, reps: int = 10, max_confi
     _check(lib().skel_tune(root.handle, arr, n, db_path.encode() if db_path else None, reps, max_configs,
                            sample_seed, ctypes.byref(best), ctypes.byref(us)))
     return best.as_dict(), us.value
+
+
+def time_config(root: Node, args, options=None, reps: int = 10):
+    """Median and minimum microseconds of one configuration (None: the default
+    plan) under the tuner's timing protocol (skel_time_config)."""
+    arr, n = _buf_array(args)
+    med = ctypes.c_double()
+    mn = ctypes.c_double()
+    _check(lib().skel_time_config(root.handle, arr, n, _opts(options), reps, ctypes.byref(med), ctypes.byref(mn)))
+    return med.value, mn.value
 
 
 def tune_batch(root: Node, reqs, db_path: str | None = None, reps: int = 10, pruned: bool = False,

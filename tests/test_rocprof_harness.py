@@ -53,3 +53,27 @@ def test_while_phases_splits_by_loop_form(tmp_path):
     assert "| host-checked | 4 | 1.27 | 1.27 |" in out
     assert "| unchecked | 5 | 1.25 | 1.25 |" in out
     assert "Step kernel: 6 dispatches, median 0.05 us." in out
+
+
+def test_driver_phase_takes_the_headline_launches(tmp_path):
+    """The headline kernel's dispatches are those before the plain plan's
+    first kernel; the last `steps` of them are the ones the bench's HIP
+    events bracket."""
+    t = [0]
+
+    def d(name, dur):
+        row = ["KERNEL_DISPATCH", name, str(t[0]), str(t[0] + dur)]
+        t[0] += dur + 10
+        return row
+
+    fused = "void skel::img_band_kernel<9, 0, true, true, 2>(skel::ImgGroupArgs)"
+    rows = []
+    for k in range(30):                     # warm-up (clock ramp), timed steps, event-bracketed launches
+        rows += [d(fused, 2000 if k < 10 else (1300 if k < 20 else 1200)),
+                 d("skel::hist_merge_kernel(skel::HistFinArgs)", 50)]
+    rows.append(d("void skel::img_band_kernel<1, 0, false, false, 0>(skel::ImgGroupArgs)", 900))
+    rows.append(d(fused, 5000))             # the same kernel later in the run (another workload)
+    p = tmp_path / "driver_kernel_trace.csv"
+    _write(p, ["Kind", "Kernel_Name", "Start_Timestamp", "End_Timestamp"], rows)
+    allf, last = rh.driver_phase(str(p), 10)
+    assert len(allf) == 30 and last == [1200] * 10
