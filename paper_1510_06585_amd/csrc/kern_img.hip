@@ -187,8 +187,12 @@ constexpr int kPrefetch = 4;
 static_assert(kPrefetch == 4, "row groups are written out for four slots (the blur ring length)");
 
 // Histogram modes: none, or one privatised histogram per work-group with
-// kHistWgChan counter words = bins x copies per channel.
-enum { HIST_NONE = 0, HIST_WG = 1 };
+// kHistWgChan counter words = bins x copies per channel.  HIST_WG: counter
+// (c, v, copy) at word c * kHistWgChan + v * copies + copy.  HIST_WG128
+// (128 bins, 16 copies): at word v * 64 + c * 16 + copy, i.e. byte address
+// v * 256 + c * 64 + 4 * copy, which one byte permute builds from the value
+// byte and the lane's copy offset (c * 64 is the instruction's offset).
+enum { HIST_NONE = 0, HIST_WG = 1, HIST_WG128 = 2 };
 constexpr int kHistWgChan = 2048;
 
 // Per-tile geometry and addressing of one image.
@@ -235,11 +239,25 @@ static __device__ __forceinline__ void band_tile(const ImgView& V, const OpList&
     const uint32_t lane_off = ((uint32_t)lane & ((1u << hks) - 1u)) * 4u;
     char* const lhb = reinterpret_cast<char*>(lh);
     auto count = [&](uint32_t e, uint32_t o, uint32_t inc) {
-        const uint32_t es = e << hsh, os = o << hsh;
-        atomicAdd(reinterpret_cast<uint32_t*>(lhb + 0 * CS * 4 + lane_off + (es & 0xFFFFu)), inc);
-        atomicAdd(reinterpret_cast<uint32_t*>(lhb + 1 * CS * 4 + lane_off + (os & 0xFFFFu)), inc);
-        atomicAdd(reinterpret_cast<uint32_t*>(lhb + 2 * CS * 4 + lane_off + (es >> 16)), inc);
-        atomicAdd(reinterpret_cast<uint32_t*>(lhb + 3 * CS * 4 + lane_off + (os >> 16)), inc);
+        if constexpr (HM == HIST_WG128) {
+            // byte 1 of the address = the value, byte 0 = the copy offset
+            // (< 64), bytes 2-3 = 0; channels R, G, B, A at offsets 0, 64,
+            // 128, 192 (e = {R, B}, o = {G, A})
+            const uint32_t aR = __builtin_amdgcn_perm(e, lane_off, 0x0C0C0400u);
+            const uint32_t aB = __builtin_amdgcn_perm(e, lane_off, 0x0C0C0600u);
+            const uint32_t aG = __builtin_amdgcn_perm(o, lane_off, 0x0C0C0400u);
+            const uint32_t aA = __builtin_amdgcn_perm(o, lane_off, 0x0C0C0600u);
+            atomicAdd(reinterpret_cast<uint32_t*>(lhb + aR), inc);
+            atomicAdd(reinterpret_cast<uint32_t*>(lhb + 64 + aG), inc);
+            atomicAdd(reinterpret_cast<uint32_t*>(lhb + 128 + aB), inc);
+            atomicAdd(reinterpret_cast<uint32_t*>(lhb + 192 + aA), inc);
+        } else {
+            const uint32_t es = e << hsh, os = o << hsh;
+            atomicAdd(reinterpret_cast<uint32_t*>(lhb + 0 * CS * 4 + lane_off + (es & 0xFFFFu)), inc);
+            atomicAdd(reinterpret_cast<uint32_t*>(lhb + 1 * CS * 4 + lane_off + (os & 0xFFFFu)), inc);
+            atomicAdd(reinterpret_cast<uint32_t*>(lhb + 2 * CS * 4 + lane_off + (es >> 16)), inc);
+            atomicAdd(reinterpret_cast<uint32_t*>(lhb + 3 * CS * 4 + lane_off + (os >> 16)), inc);
+        }
     };
 
     // The row sweep, instantiated once for interior bands (one 16-byte load
@@ -449,14 +467,14 @@ static __device__ __forceinline__ void band_tile(const ImgView& V, const OpList&
 // starts each bin's copy sum at a different copy to spread LDS banks.
 // With CLEAR every counter is zeroed after it is read (each word is read by
 // one thread only), leaving the histogram ready for the next tile group.
-template <int CS, bool CLEAR = false>
+template <int CS, bool CLEAR = false, bool L128 = false>
 static __device__ __forceinline__ void write_hist_row(uint32_t* lh, int hks, uint32_t* row, int first, int step) {
     const int copies = 1 << hks;
     const int bins = CS >> hks;
     for (int b = first; b < 4 * bins; b += step) {
         const int c = b >> (__builtin_ctz((unsigned)bins));
         const int v = b & (bins - 1);
-        uint32_t* w = lh + c * CS + (v << hks);
+        uint32_t* w = L128 ? lh + v * 64 + c * 16 : lh + c * CS + (v << hks);
         uint32_t n = 0;
         for (int j = 0; j < copies; ++j) {
             n += w[(j + v) & (copies - 1)];
@@ -495,13 +513,21 @@ __global__ void __launch_bounds__(256) img_band_kernel(const ImgGroupArgs A) {
         const int y1 = min(y0 + A.tile_h, A.H);
         const ImgView V{A.in, A.out, A.W, A.H, FL < 0 ? A.in_flip : (FL & 1), FL < 0 ? A.out_flip : (FL >> 1),
                         A.write_out};
-        band_tile<PRE, POST, BLUR, HIST ? HIST_WG : HIST_NONE>(V, A.pre, A.post, band, y0, y1, lane, lh,
-                                                                A.hist_ks);
+        if (HIST && A.bins == 128)
+            band_tile<PRE, POST, BLUR, HIST ? HIST_WG128 : HIST_NONE>(V, A.pre, A.post, band, y0, y1, lane, lh,
+                                                                       A.hist_ks);
+        else
+            band_tile<PRE, POST, BLUR, HIST ? HIST_WG : HIST_NONE>(V, A.pre, A.post, band, y0, y1, lane, lh,
+                                                                    A.hist_ks);
     }
     if constexpr (HIST) {
         __syncthreads();
-        write_hist_row<kHistWgChan>(lh, A.hist_ks, A.part + (size_t)blockIdx.x * 4 * A.bins, threadIdx.x,
-                                    blockDim.x);
+        if (A.bins == 128)
+            write_hist_row<kHistWgChan, false, true>(lh, A.hist_ks, A.part + (size_t)blockIdx.x * 4 * A.bins,
+                                                     threadIdx.x, blockDim.x);
+        else
+            write_hist_row<kHistWgChan>(lh, A.hist_ks, A.part + (size_t)blockIdx.x * 4 * A.bins, threadIdx.x,
+                                        blockDim.x);
     }
 }
 
@@ -556,13 +582,21 @@ __global__ void __launch_bounds__(256) img_batch_kernel(const BatchArgs A) {
             const int y1 = min(y0 + R.tile_h, R.H);
             const ImgView V{R.in, R.out, R.W, R.H, FL < 0 ? A.in_flip : (FL & 1), FL < 0 ? A.out_flip : (FL >> 1),
                             1};
-            band_tile<PRE, POST, BLUR, HIST ? HIST_WG : HIST_NONE>(V, A.pre, A.post, band, y0, y1, lane, lh,
-                                                                    A.hist_ks);
+            if (HIST && A.bins == 128)
+                band_tile<PRE, POST, BLUR, HIST ? HIST_WG128 : HIST_NONE>(V, A.pre, A.post, band, y0, y1, lane, lh,
+                                                                           A.hist_ks);
+            else
+                band_tile<PRE, POST, BLUR, HIST ? HIST_WG : HIST_NONE>(V, A.pre, A.post, band, y0, y1, lane, lh,
+                                                                        A.hist_ks);
         }
         if constexpr (HIST) {
             __syncthreads();
-            write_hist_row<kHistWgChan, true>(lh, A.hist_ks, A.part + (size_t)g * 4 * A.bins, threadIdx.x,
-                                              blockDim.x);
+            if (A.bins == 128)
+                write_hist_row<kHistWgChan, true, true>(lh, A.hist_ks, A.part + (size_t)g * 4 * A.bins, threadIdx.x,
+                                                        blockDim.x);
+            else
+                write_hist_row<kHistWgChan, true>(lh, A.hist_ks, A.part + (size_t)g * 4 * A.bins, threadIdx.x,
+                                                  blockDim.x);
         }
     }
 }
