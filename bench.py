@@ -601,6 +601,8 @@ def main():
     ap.add_argument("--no-selector", action="store_true", help="leave the learned-selector experiment out of the extras")
     ap.add_argument("--selector-dir", default=None, help="where the selector experiment keeps its databases")
     ap.add_argument("--selector-train", type=int, default=1000)
+    ap.add_argument("--selector-sampled-only", action="store_true",
+                    help="train on sampled labels only (without each training composition's Algorithm-1 walk)")
     ap.add_argument("--selector-test", type=int, default=200)
     a = ap.parse_args()
     if a.gpus != 1:
@@ -629,7 +631,8 @@ def main():
     if a.selector:
         from paper_1510_06585_amd import selector
         print(json.dumps(selector.experiment(n_train=a.selector_train, n_test=a.selector_test,
-                                             workdir=a.selector_dir, log=log)), flush=True)
+                                             workdir=a.selector_dir, log=log,
+                                             train_pruned=not a.selector_sampled_only)), flush=True)
         return
     log("config 2: fused pipeline + mapreduce 8192x8192")
     out, img = bench_fused_mapreduce_8192(a.steps, a.warmup, not a.no_cpu_baseline)

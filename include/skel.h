@@ -458,7 +458,9 @@ skel_status skel_cost_train(const char* db_path, const char* weights_out, int32_
 
 /* Scores every valid configuration of (root, shapes) with the trained model
  * in `weights` (one GPU forward pass over all candidates) and writes the one
- * with the lowest predicted runtime to *chosen. */
+ * with the lowest predicted runtime to *chosen.  `weights` may list several
+ * model files separated by ';' (an ensemble): their log-runtime predictions
+ * are averaged (also for skel_cost_rank). */
 skel_status skel_cost_select(skel_node root, const skel_buffer* proto, int32_t nargs,
                              const char* weights, skel_plan_opts* chosen);
 

@@ -236,10 +236,24 @@ namespace {
 
 // Every valid configuration of the composition with its predicted run time
 // (log microseconds), from one forward pass of the model over all of them.
+// `weights` may name several models separated by ';' (an ensemble, e.g. the
+// same data trained from different initialisations): the prediction is the
+// mean of their log-time predictions.
 skel_status predict_all(skel_node root, const skel_buffer* proto, int32_t nargs, const char* weights,
                         std::vector<Config>& cands, std::vector<float>& Y) {
-    Model m;
-    if (!load_model(weights, m)) return set_error(SKEL_EINVAL, "cannot read cost model %s", weights);
+    std::vector<std::string> paths;
+    {
+        std::string w(weights);
+        size_t a = 0;
+        while (a <= w.size()) {
+            const size_t b = w.find(';', a);
+            const std::string one = w.substr(a, b == std::string::npos ? std::string::npos : b - a);
+            if (!one.empty()) paths.push_back(one);
+            if (b == std::string::npos) break;
+            a = b + 1;
+        }
+    }
+    if (paths.empty()) return set_error(SKEL_EINVAL, "no cost model named");
     Linear L;
     Shape sh;
     skel_status st = linearize(root, L);
@@ -249,24 +263,29 @@ skel_status predict_all(skel_node root, const skel_buffer* proto, int32_t nargs,
     cands = enumerate_configs(L, sh);
     if (cands.empty()) return set_error(SKEL_EUNSUPPORTED, "no valid configuration");
     const int n = (int)cands.size();
-    std::vector<float> X((size_t)n * kNumFeatures);
-    for (int i = 0; i < n; ++i) {
-        features(L, sh, cands[i], &X[(size_t)i * kNumFeatures]);
-        for (int j = 0; j < kNumFeatures; ++j)
-            X[(size_t)i * kNumFeatures + j] = (X[(size_t)i * kNumFeatures + j] - m.mean[j]) / m.stdv[j];
-    }
-    float *dP = nullptr, *dX = nullptr, *dY = nullptr;
-    hipError_t e = hipMalloc(&dP, sizeof(float) * kNP);
-    if (!e) e = hipMalloc(&dX, sizeof(float) * X.size());
-    if (!e) e = hipMalloc(&dY, sizeof(float) * n);
-    if (!e) e = hipMemcpy(dP, m.theta.data(), sizeof(float) * kNP, hipMemcpyHostToDevice);
-    if (!e) e = hipMemcpy(dX, X.data(), sizeof(float) * X.size(), hipMemcpyHostToDevice);
-    if (!e) e = launch_mlp_forward(dP, dX, n, dY, nullptr);
+    std::vector<float> F((size_t)n * kNumFeatures);
+    for (int i = 0; i < n; ++i) features(L, sh, cands[i], &F[(size_t)i * kNumFeatures]);
     Y.assign(n, 0.0f);
-    if (!e) e = hipMemcpy(Y.data(), dY, sizeof(float) * n, hipMemcpyDeviceToHost);
-    for (void* q : {(void*)dP, (void*)dX, (void*)dY})
-        if (q) (void)hipFree(q);
-    if (e != hipSuccess) return set_error(SKEL_EDEVICE, "cost model inference: %s", hipGetErrorString(e));
+    std::vector<float> X(F.size()), Yk(n);
+    for (const std::string& path : paths) {
+        Model m;
+        if (!load_model(path.c_str(), m)) return set_error(SKEL_EINVAL, "cannot read cost model %s", path.c_str());
+        for (int i = 0; i < n; ++i)
+            for (int j = 0; j < kNumFeatures; ++j)
+                X[(size_t)i * kNumFeatures + j] = (F[(size_t)i * kNumFeatures + j] - m.mean[j]) / m.stdv[j];
+        float *dP = nullptr, *dX = nullptr, *dY = nullptr;
+        hipError_t e = hipMalloc(&dP, sizeof(float) * kNP);
+        if (!e) e = hipMalloc(&dX, sizeof(float) * X.size());
+        if (!e) e = hipMalloc(&dY, sizeof(float) * n);
+        if (!e) e = hipMemcpy(dP, m.theta.data(), sizeof(float) * kNP, hipMemcpyHostToDevice);
+        if (!e) e = hipMemcpy(dX, X.data(), sizeof(float) * X.size(), hipMemcpyHostToDevice);
+        if (!e) e = launch_mlp_forward(dP, dX, n, dY, nullptr);
+        if (!e) e = hipMemcpy(Yk.data(), dY, sizeof(float) * n, hipMemcpyDeviceToHost);
+        for (void* q : {(void*)dP, (void*)dX, (void*)dY})
+            if (q) (void)hipFree(q);
+        if (e != hipSuccess) return set_error(SKEL_EDEVICE, "cost model inference: %s", hipGetErrorString(e));
+        for (int i = 0; i < n; ++i) Y[i] += Yk[i] / (float)paths.size();
+    }
     return SKEL_OK;
 }
 

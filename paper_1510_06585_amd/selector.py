@@ -10,8 +10,11 @@ plan and tile configuration for compositions it has never seen:
    5x5 blur / saxpy, mirror, optional sum reduce; 2^16..2^26 elements), split
    by composition into a training set and a held-out set;
 2. time a sample of configurations of every training composition with the
-   auto-tuner (labels), and every configuration of every held-out composition
-   (exhaustive: its best is the reference);
+   auto-tuner, plus the configurations Algorithm 1's walk times for it (the
+   profiles the paper's knowledge base holds), as labels; and every
+   configuration of every held-out composition (exhaustive: its best is the
+   reference), the default plan and the re-timed best and runner-up with the
+   same protocol;
 3. train the MLP on the GPU (skel_cost_train) and let it pick a configuration
    for each held-out composition (skel_cost_select), or shortlist its k best
    (skel_cost_rank) for the profiler to time (scored here as the fastest
@@ -107,8 +110,11 @@ def _stats(reg):
 
 
 def experiment(n_train: int = 1000, n_test: int = 200, per_train: int = 20, seed: int = 5,
-               epochs: int = 200, workdir: str | None = None, log=print, noise_check: bool = True):
-    """Runs the experiment; with noise_check, every held-out composition's
+               epochs: int = 200, workdir: str | None = None, log=print, noise_check: bool = True,
+               train_pruned: bool = True):
+    """Runs the experiment; with train_pruned, every training composition's
+    sampled labels are joined by the configurations the Algorithm-1 walk
+    times for it; with noise_check, every held-out composition's
     best and runner-up configurations are re-timed twice more once its labels
     and its pruned search are done (fresh plans, the same protocol: 3 warm-up
     runs, median of 10), giving the labels' run-to-run noise floor."""
@@ -139,6 +145,10 @@ def experiment(n_train: int = 1000, n_test: int = 200, per_train: int = 20, seed
         root = sk.image_chain(c["stages"], c["reduce"])
         args = _args_for(c, gen)
         sk.tune(root, args, train_db, reps=5, max_configs=per_train, sample_seed=seed * 100003 + i)
+        if train_pruned:
+            # Algorithm 1's walk adds the rows around the composition's best
+            # to the knowledge base (the profiles the paper stores)
+            sk.tune_pruned(root, args, train_db, reps=5)
         del args
         if i % 50 == 0:
             log(f"train {i}/{len(train)} {time.time() - t0:.0f}s")
@@ -175,6 +185,14 @@ def experiment(n_train: int = 1000, n_test: int = 200, per_train: int = 20, seed
     t1 = time.time()
     loss = sk.cost_train(train_db, weights, epochs, seed=seed, init=init)
     t_train = time.time() - t1
+    # an ensemble of three networks trained on the same rows from different
+    # initialisations and sample orders; selection averages their predictions
+    ens = [weights]
+    for k in (1, 2):
+        wk = os.path.join(workdir, f"cost_model_{k}.txt")
+        sk.cost_train(train_db, wk, epochs, seed=seed + k, init=synth.mlp_init(seed + k).astype(np.float32))
+        ens.append(wk)
+    weights_ens = ";".join(ens)
     loss0 = sk.cost_train(train_db, weights0, 0, seed=seed, init=init)
     # nearest-neighbour derivation over the training rows (standardised features)
     tr = _read_rows(train_db)
@@ -183,13 +201,14 @@ def experiment(n_train: int = 1000, n_test: int = 200, per_train: int = 20, seed
     mu, sd = F.mean(0), F.std(0)
     sd[sd < 1e-6] = 1.0
     Fz = (F - mu) / sd
-    reg = {"model": [], "model_top3_timed": [], "model_top5_timed": [], "default": [], "nearest_neighbour": [],
+    reg = {"model": [], "model_ensemble3": [], "model_top3_timed": [], "model_top5_timed": [], "default": [],
+           "nearest_neighbour": [],
            "rbf": [], "untrained": [], "random": [], "pruned_tuner": []}
     for c, rows, tdef, (popts, _) in zip(test, test_rows, defaults, pruned):
         root = sk.image_chain(c["stages"], c["reduce"])
         protos = _args_for_proto(c)
         best = min(r["t"] for r in rows)
-        for name, w in (("model", weights), ("untrained", weights0)):
+        for name, w in (("model", weights), ("model_ensemble3", weights_ens), ("untrained", weights0)):
             o = sk.cost_select(root, protos, w)
             t = _match(rows, o)
             reg[name].append((t if t is not None else tdef) / best - 1.0)
@@ -230,6 +249,7 @@ def experiment(n_train: int = 1000, n_test: int = 200, per_train: int = 20, seed
                                "configuration, two re-timings each (median of 10 runs after 3 warm-ups)"}
     return {
         "experiment": "learned config selector",
+        "train_pruned": bool(train_pruned),
         "label_noise": label_noise,
         "train_compositions": len(train), "heldout_compositions": len(test), "labels": n_labels,
         "heldout_configs_timed": int(sum(len(r) for r in test_rows)),
