@@ -136,3 +136,42 @@ def test_batch_tuner_choice_matches_oracle(tmp_path):
             assert (a[2].cpu().numpy().view(np.uint32) == rh).all()
             assert (a[3].cpu().numpy().view(np.uint64) == rs).all()
         p.destroy()
+
+
+def test_batch_at_the_request_limit():
+    """65535 requests (the tile -> request table holds 16-bit request
+    indices), tiny images of 1..3 x 1..5 pixels carved from one buffer, in
+    one persistent launch: every request's image, histogram and sums equal the
+    oracle's; one more request is rejected."""
+    n = 65535
+    rng = np.random.default_rng(29)
+    Hs = rng.integers(1, 4, n)
+    Ws = rng.integers(1, 6, n)
+    px = Hs * Ws
+    off = np.concatenate([[0], np.cumsum(px)])
+    flat_in = rng.integers(0, 256, (int(off[-1]), 4), dtype=np.uint8)
+    x = cuda(flat_in)
+    y = torch.empty_like(x)
+    hist = torch.full((n, 4, 256), 5, dtype=torch.int32, device="cuda")
+    sums = torch.full((n, 4), 5, dtype=torch.int64, device="cuda")
+    reqs = []
+    for r in range(n):
+        a, b = int(off[r]), int(off[r + 1])
+        reqs.append([x[a:b].view(int(Hs[r]), int(Ws[r]), 4), y[a:b].view(int(Hs[r]), int(Ws[r]), 4), hist[r],
+                     sums[r]])
+    p = plan_for(PIPE_NSBM)
+    p.batch_run(reqs)
+    torch.cuda.synchronize()
+    out = y.cpu().numpy()
+    hh = hist.cpu().numpy().view(np.uint32)
+    ss = sums.cpu().numpy().view(np.uint64)
+    for r in range(0, n, 1):
+        a, b = int(off[r]), int(off[r + 1])
+        img = flat_in[a:b].reshape(int(Hs[r]), int(Ws[r]), 4)
+        ref, rh, rs = oracle.run_image_pipeline(img, PIPE_NSBM, "hist_sum")
+        assert (out[a:b].reshape(ref.shape) == ref).all(), r
+        assert (hh[r] == rh).all() and (ss[r] == rs).all(), r
+    with pytest.raises(sk.SkelError) as e:
+        p.batch_run(reqs + [reqs[0]])
+    assert e.value.status == sk.EUNSUPPORTED
+    p.destroy()

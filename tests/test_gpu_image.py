@@ -194,3 +194,20 @@ def test_wrong_shapes_rejected_at_run():
     with pytest.raises(sk.SkelError) as e:
         p.run(bad)
     assert e.value.status == sk.ESHAPE
+
+
+@pytest.mark.parametrize("H,W", [(3, 65536), (65536, 3), (2, 65535)], ids=["3x65536", "65536x3", "2x65535"])
+def test_image_side_at_the_65536_limit(H, W):
+    """Sides at the noise key's 16-bit limit (x and y up to 65535 packed in
+    one 32-bit key): the full chain with histogram and sums, fused and
+    unfused, against the oracle; a side of 65537 is rejected."""
+    img = synth.image(H + 3 * W, H, W)
+    ref, rh, rs = oracle.run_image_pipeline(img, PIPE_NSBM, "hist_sum")
+    for options in ({}, {"fusion": sk.FUSE_OFF}):
+        out, h, s = run_image(PIPE_NSBM, img, "hist_sum", options)
+        assert_image_equal(out, ref, f"{H}x{W} {options}")
+        assert (h == rh).all() and (s == rs).all()
+    big = [sk.proto([H, 65537, 4] if W >= H else [65537, W, 4], sk.U8)] * 2
+    with pytest.raises(sk.SkelError) as e:
+        sk.Plan(sk.image_chain(PIPE_NSBM), big)
+    assert e.value.status == sk.EUNSUPPORTED

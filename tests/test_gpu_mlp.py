@@ -231,6 +231,7 @@ def test_trained_model_against_the_methods_without_it(tmp_path):
     reg = r["regret"]
     print({k: v["mean"] for k, v in reg.items()}, r["label_noise"]["rel_diff"])
     assert reg["model"]["mean"] <= 0.10
+    assert reg["model_ensemble3"]["mean"] <= 0.10
     assert reg["model"]["mean"] < 0.5 * reg["untrained"]["mean"]
     assert reg["model"]["mean"] < 0.5 * reg["random"]["mean"]
     assert r["label_noise"]["rel_diff"]["median"] < 0.03
