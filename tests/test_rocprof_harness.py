@@ -77,3 +77,12 @@ def test_driver_phase_takes_the_headline_launches(tmp_path):
     _write(p, ["Kind", "Kernel_Name", "Start_Timestamp", "End_Timestamp"], rows)
     allf, last = rh.driver_phase(str(p), 10)
     assert len(allf) == 30 and last == [1200] * 10
+
+
+def test_last_dispatches_mean(tmp_path):
+    rows = [["KERNEL_DISPATCH", "void skel::img_batch_kernel<9>(x)", str(100 * i), str(100 * i + d)]
+            for i, d in enumerate([50, 60, 10, 20, 30])]
+    p = tmp_path / "t.csv"
+    _write(p, ["Kind", "Kernel_Name", "Start_Timestamp", "End_Timestamp"], rows)
+    assert rh.last_dispatches(str(p), "img_batch_kernel", 3) == 20.0
+    assert rh.last_dispatches(str(p), "img_batch_kernel", 6) is None
