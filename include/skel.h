@@ -340,10 +340,12 @@ skel_status skel_plan_run_noalloc(skel_plan plan, const skel_buffer* args, int32
 skel_status skel_plan_describe(skel_plan plan, char* buf, size_t len);
 
 /* Measurement hook: while set, every run of the plan records hipEvent_t
- * `start` on its stream immediately before launching kernel `kernel` (an
- * index into the kernels skel_plan_describe lists) and `end` immediately
- * after it, so the kernel's own duration can be read with
- * hipEventElapsedTime.  kernel < 0 or NULL events clear the hook.  Not
+ * `start` and `end` around kernel `kernel` (an index into the kernels
+ * skel_plan_describe lists), so the kernel's own duration can be read with
+ * hipEventElapsedTime.  Image kernels take both timestamps from their own
+ * dispatch (hipExtLaunchKernel), which brackets the kernel's execution
+ * exactly; other kernels have the events recorded on the stream immediately
+ * before and after the launch.  kernel < 0 or NULL events clear the hook.  Not
  * applied inside captured graphs (N-body loops, batched runs).  The caller
  * owns the events. */
 skel_status skel_plan_kernel_events(skel_plan plan, int32_t kernel, void* start, void* end);

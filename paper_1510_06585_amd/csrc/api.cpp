@@ -147,9 +147,8 @@ skel_status run_image(skel_plan p, const skel_buffer* args, hipStream_t s) {
             A.sum = L.red == SKEL_RED_HIST256_SUM ? (uint64_t*)args[3].data : (uint64_t*)args[2].data;
         }
         const bool prof = (int)ki == p->prof_kernel;
-        if (prof) HIP_TRY(hipEventRecord(p->prof_start, s));
-        HIP_TRY(launch_img_group(A, k.blur, k.reduce, k.wg, p->cfg.variant, s, &k.name));
-        if (prof) HIP_TRY(hipEventRecord(p->prof_end, s));
+        HIP_TRY(launch_img_group(A, k.blur, k.reduce, k.wg, p->cfg.variant, s, &k.name, prof ? p->prof_start : nullptr,
+                                 prof ? p->prof_end : nullptr));
         if (k.reduce) {
             // Add the work-groups' histogram rows to the outputs, which
             // work-group 0 of the kernel cleared (or clear them: no tiles).

@@ -59,9 +59,10 @@ int encode_ops(const OpList& l);
 
 // Launches one fused image kernel with `wg` threads per work-group (64, 128
 // or 256).  variant 1 forces the generic interpreter.  *kname receives the
-// kernel's name.
+// kernel's name.  t0 / t1 (may be null): events timestamped by the kernel's
+// own dispatch (start and end of its execution).
 hipError_t launch_img_group(const ImgGroupArgs& a, bool blur, bool hist, int wg, int variant,
-                            hipStream_t s, const char** kname);
+                            hipStream_t s, const char** kname, hipEvent_t t0 = nullptr, hipEvent_t t1 = nullptr);
 
 const char* img_kernel_name(const ImgGroupArgs& a, bool blur, bool hist, int variant);
 // Resident wavefronts per CU of the kernel launch_img_group would pick (16

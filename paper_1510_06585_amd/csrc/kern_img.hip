@@ -16,6 +16,8 @@
 // e = {R, B} and o = {G, A}.  Noise/solarise use packed 16-bit VALU ops.  Box
 // sums stay below 6375 per channel, so packed 32-bit adds never carry between
 // the halves and DPP wave shifts fold the neighbour exchange into the adds.
+#include <hip/hip_ext.h>
+
 #include "kern_common.h"
 #include "kern.h"
 
@@ -862,13 +864,26 @@ const char* img_kernel_name(const ImgGroupArgs& a, bool blur, bool hist, int var
 }
 
 hipError_t launch_img_group(const ImgGroupArgs& a, bool blur, bool hist, int wg, int variant, hipStream_t s,
-                            const char** kname) {
+                            const char** kname, hipEvent_t t0, hipEvent_t t1) {
     const ImgEntry* e = find_entry(a.pre, a.post, blur, hist, a.in_flip, a.out_flip, variant);
     if (!e) return hipErrorInvalidValue;
     if (kname) *kname = e->name;
-    if (a.ntiles <= 0) return hipSuccess;
+    if (a.ntiles <= 0) {
+        // nothing to launch: the requested events still mark this point
+        hipError_t r = t0 ? hipEventRecord(t0, s) : hipSuccess;
+        if (r == hipSuccess && t1) r = hipEventRecord(t1, s);
+        return r;
+    }
     const int waves = wg / 64;
     const int grid = (a.ntiles + waves - 1) / waves;
+    if (t0 || t1) {
+        // the events take their timestamps from the kernel's own dispatch,
+        // so they bracket its execution and nothing else
+        ImgGroupArgs arg = a;
+        void* args[] = {&arg};
+        return hipExtLaunchKernel(reinterpret_cast<const void*>(e->fn), dim3(grid), dim3(wg), args, 0, s, t0, t1,
+                                  0);
+    }
     hipLaunchKernelGGL(e->fn, dim3(grid), dim3(wg), 0, s, a);
     return hipGetLastError();
 }
