@@ -306,7 +306,7 @@ def bench_nbody():
                        "frac_of_non_packed_fp32_peak": round(tflops / FP32_NONPACKED_TFLOPS, 4),
                        "note": f"{NBODY_FLOPS_PER_PAIR} flops per pair interaction by convention; peak = MI355X "
                                f"published FP32 vector rate (packed FP32), {FP32_NONPACKED_TFLOPS} without "
-                               f"packed FP32 instructions, which this build does not use"}
+                               f"packed FP32 instructions, which this library does not emit"}
     issue_peak = VALU_LANE_OPS / NBODY_LANE_OPS_PER_PAIR
     res["issue_efficiency"] = {"achieved_ginteractions_s": round(rate / 1e9, 2),
                                "issue_bound_ginteractions_s": round(issue_peak / 1e9, 2),
