@@ -392,27 +392,21 @@ extern "C" skel_status skel_time_config(skel_node root, const skel_buffer* args,
                                         double* min_us) {
     clear_error();
     if (!root || !median_us) return set_error(SKEL_EINVAL, "null root or result");
-    Linear L;
-    Shape sh;
-    Config c;
-    skel_status st = linearize(root, L);
-    if (!st && L.dom == DOM_NONE) L.dom = (nargs > 0 && args[0].dtype == SKEL_U8) ? DOM_U8 : DOM_F32;
-    if (!st) st = derive_shape(L, args, nargs, sh);
-    if (!st) st = resolve_config(L, sh, opts, c);
-    if (st) return st;
     if (reps <= 0) reps = 10;
     skel_plan_opts o;
     if (opts) o = *opts; else skel_plan_opts_default(&o);
+    // Compile once up front so that an invalid request reports the plan
+    // compiler's own status and message (the timer folds compile failures
+    // into SKEL_EINVAL); the options are passed on as given, so defaults such
+    // as fitted tile heights stay defaults.
+    skel_plan p = nullptr;
+    skel_status st = skel_plan_compile(root, args, nargs, &o, &p);
+    if (st) return st;
+    skel_plan_destroy(p);
     Timer T;
     if ((st = T.init())) return st;
     double med = 0, mn = 0;
-    // Timer::time compiles from options; pass the caller's as given so that
-    // defaults (auto tile heights) stay defaults
-    skel_plan p = nullptr;
-    if ((st = skel_plan_compile(root, args, nargs, &o, &p))) return st;
-    skel_plan_destroy(p);
-    st = T.time_opts(root, args, nargs, o, reps, &med, &mn);
-    if (st) return st;
+    if ((st = T.time_opts(root, args, nargs, o, reps, &med, &mn))) return st;
     *median_us = med;
     if (min_us) *min_us = mn;
     return SKEL_OK;
