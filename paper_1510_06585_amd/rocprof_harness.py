@@ -289,10 +289,13 @@ def main():
         cw = ["# rocprofv3 summary: while Loop, noise > solarise > blur > mirror + histogram body over "
               "8192x8192 RGBA u8, 10 iterations", "",
               "Command (repository root on the MI355X host, TMPDIR=/tmp):", "", "```", COMMAND_WHILE, "```", "",
-              "The run times the while plan (13 runs: 3 warm-up, 10 timed), the same body with the sums read "
-              "back by the host after every iteration (6 runs) and the body alone, unchecked (6 runs), "
-              "10 iterations each.  Per iteration the while plan launches the image kernel, the histogram "
-              "merge and the one-thread step kernel; per run one init kernel and one final guarded copy.", "",
+              "The run times, 10 iterations each, the while plan with host checks in blocks of 8 and then the "
+              "asynchronous while plan with the convergence condition and both reduce outputs carried (each "
+              "after the warm-up floor, then 10 timed runs; both count as \"while plan\" below), the same body "
+              "with the sums read back by the host after every iteration and the body alone, unchecked.  Per "
+              "iteration a while plan launches the image kernel, the histogram merge and the step kernel "
+              "(one work-group: the carried merges, the count and the condition); per run one init kernel "
+              "and one final guarded copy.", "",
               "| kernel | calls | avg us | min us | max us |", "|---|---|---|---|---|"]
         for r in stats:
             cw.append(f"| `{r['name'][:90]}` | {r['calls']} | {r['avg_ns']/1e3:.2f} | {r['min_ns']/1e3:.2f} | "
@@ -310,9 +313,12 @@ def main():
             cw += while_phases(a.while_dispatches)
         if a.while_json:
             w = json.loads([ln for ln in open(a.while_json) if ln.startswith("{")][-1])
+            asy = w.get("async_delta_carried_ms_per_iteration")
             cw += ["", "Wall time per iteration under the profiler (ms): "
-                   f"while plan {w['device_condition_ms_per_iteration']}, host-checked body "
-                   f"{w['host_condition_ms_per_iteration']}, unchecked body {w['no_condition_ms_per_iteration']}."]
+                   f"while plan {w['device_condition_ms_per_iteration']}"
+                   + (f", asynchronous while plan (convergence condition, carried outputs) {asy}" if asy else "")
+                   + f", host-checked body {w['host_condition_ms_per_iteration']}, unchecked body "
+                   f"{w['no_condition_ms_per_iteration']}."]
         open(os.path.join(a.out, "while_loop_8192.md"), "w").write("\n".join(cw) + "\n")
     if a.mlp_counters:
         cm = counters(a.mlp_counters)
