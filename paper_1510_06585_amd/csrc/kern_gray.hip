@@ -10,11 +10,17 @@
 // image of each class under stages 2..k: out = c0, c1 or c2 for v < lo1,
 // lo1 <= v < hi1, v >= hi1.  Every wavefront folds the chain into
 // (lo1, hi1, c0, c1, c2) once with uniform (scalar) arithmetic, so a voxel
-// costs the same for any chain length.  A word's four bytes are split into
-// two u16 pairs, bytes {0, 2} and {1, 3}; per pair, ge(v, t) =
-// min(sat(v + 1 - t), 1) is 1 when v >= t, and the class value is
-// c0 + ge(v, lo1) (c1 - c0) + ge(v, hi1) (c2 - c1) in 16-bit modular
-// arithmetic (ge(v, hi1) = 1 implies ge(v, lo1) = 1, as lo1 <= hi1).
+// costs the same for any chain length.
+//
+// The four voxels of a 32-bit word are classified together, one byte per
+// voxel.  v_lerp_u8 gives (a + b + 1) >> 1 for every byte; with b = 255 - t
+// the sum reaches 256, i.e. bit 7 of the byte is set, exactly when v >= t.
+// Two of them give the byte selector s = [v >= lo1] + 2 [v >= hi1] in
+// {0, 1, 3}, and one byte permute of the word {c0, c1, -, c(255)} by s gives
+// the four outputs: 7 instructions per word for any thresholds.  A threshold
+// of 256 is clamped to 255, which only changes the selector of v = 255;
+// entry 3 is therefore the class of 255 itself (c2, or c1 when hi1 = 256, or
+// c0 when lo1 = 256).
 #include "kern_common.h"
 #include "kern.h"
 
@@ -23,8 +29,8 @@ namespace skel {
 constexpr int kGrayBatch = 4;   // 16-byte loads in flight per lane
 
 struct GrayFold {
-    uint32_t lo, hi;     // first stage's thresholds
-    uint32_t c0, d1, d2; // class 0 value, class 1 - class 0, class 2 - class 1 (mod 2^16)
+    uint32_t blo, bhi;   // (255 - min(lo1, 255)) and (255 - min(hi1, 255)) in every byte
+    uint32_t lut;        // bytes: c0, c1, 0, class of 255
 };
 
 static __device__ __forceinline__ uint32_t seg_scalar(uint32_t v, uint32_t lo, uint32_t hi) {
@@ -35,23 +41,17 @@ static __device__ __forceinline__ GrayFold fold_chain(const GrayArgs& A) {
     uint32_t c[3] = {0u, 128u, 255u};
     for (int k = 1; k < A.nops; ++k)
         for (int j = 0; j < 3; ++j) c[j] = seg_scalar(c[j], A.lo[k], A.hi[k]);
-    return {A.lo[0], A.hi[0], c[0], (c[1] - c[0]) & 0xFFFFu, (c[2] - c[1]) & 0xFFFFu};
-}
-
-static __device__ __forceinline__ u16x2 ge_pair(u16x2 v1, uint32_t t) {
-    // v1 = v + 1; sat(v + 1 - t) capped at 1
-    return __builtin_elementwise_min(__builtin_elementwise_sub_sat(v1, (u16x2)(unsigned short)t), (u16x2)1);
-}
-
-static __device__ __forceinline__ u16x2 classify_pair(u16x2 v, const GrayFold& F) {
-    const u16x2 v1 = v + (u16x2)1;
-    return (u16x2)(unsigned short)F.c0 + ge_pair(v1, F.lo) * (u16x2)(unsigned short)F.d1 +
-           ge_pair(v1, F.hi) * (u16x2)(unsigned short)F.d2;
+    const uint32_t lo = A.lo[0], hi = A.hi[0];
+    const uint32_t top = 255u < lo ? c[0] : (255u < hi ? c[1] : c[2]);
+    return {(255u - min(lo, 255u)) * 0x01010101u, (255u - min(hi, 255u)) * 0x01010101u,
+            c[0] | (c[1] << 8) | (top << 24)};
 }
 
 static __device__ __forceinline__ uint32_t segment_word(uint32_t w, const GrayFold& F) {
-    const u16x2 e = as16(w & 0x00FF00FFu), o = as16(__builtin_amdgcn_perm(0u, w, 0x0C030C01u));
-    return as32(classify_pair(e, F)) | (as32(classify_pair(o, F)) << 8);
+    const uint32_t glo = __builtin_amdgcn_lerp(w, F.blo, 0x01010101u);   // bit 7 of byte i: v_i >= lo1
+    const uint32_t ghi = __builtin_amdgcn_lerp(w, F.bhi, 0x01010101u);   // bit 7 of byte i: v_i >= hi1
+    const uint32_t sel = ((glo >> 7) & 0x01010101u) | ((ghi >> 6) & 0x02020202u);
+    return __builtin_amdgcn_perm(0u, F.lut, sel);
 }
 
 __global__ void __launch_bounds__(1024) gray_chain_kernel(const GrayArgs A) {

@@ -53,6 +53,23 @@ def test_all_256_values_and_degenerate_thresholds():
         _check(vol, [(lo, hi)])
 
 
+def test_threshold_grid_on_every_byte_value():
+    """Every byte value under each pair of thresholds drawn from the edges
+    (0, 1, 2, 127, 128, 129, 254, 255, 256) and under 200 random pairs, one
+    stage at a time and chained three at a time (the chain's fold)."""
+    vol = np.tile(np.arange(256, dtype=np.uint8), 4).reshape(4, 256)
+    edges = [0, 1, 2, 127, 128, 129, 254, 255, 256]
+    pairs = [(a, b) for a in edges for b in edges if a <= b]
+    rng = np.random.default_rng(77)
+    for _ in range(200):
+        a, b = sorted(int(t) for t in rng.integers(0, 257, 2))
+        pairs.append((a, b))
+    for lo, hi in pairs:
+        _check(vol, [(lo, hi)])
+    for i in range(0, len(pairs) - 2, 3):
+        _check(vol, pairs[i:i + 3])
+
+
 @pytest.mark.parametrize("fusion", ["on", "off", "mask"])
 def test_chains_fused_and_unfused(fusion):
     vol = synth.gray_volume(synth.SEED_SEGMENT + 1, 33, 100, 101)
