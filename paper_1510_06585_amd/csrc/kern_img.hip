@@ -184,9 +184,12 @@ static __device__ __forceinline__ uint32_t div25_pair(uint32_t s) {
 
 static __device__ __forceinline__ int clampi(int v, int lo, int hi) { return v < lo ? lo : (v > hi ? hi : v); }
 
-// Input rows in flight per wavefront ahead of the row being computed.
+// Input rows in flight per wavefront ahead of the row being computed
+// (pointwise chains; a blur keeps one per slot of its 5-row ring).
 constexpr int kPrefetch = 4;
-static_assert(kPrefetch == 4, "row groups are written out for four slots (the blur ring length)");
+static_assert(kPrefetch == 4, "pointwise row groups are written out for four slots");
+constexpr int kBlurRing = 5;
+static_assert(kBlurRing == 5, "blur row groups are written out for five slots");
 
 // Histogram modes: none, or one privatised histogram per work-group with
 // kHistWgChan counter words = bins x copies per channel.  HIST_WG: counter
@@ -391,9 +394,15 @@ static __device__ __forceinline__ void band_tile(const ImgView& V, const OpList&
             if (rem > 1) row(std::integral_constant<int, 1>{}, y + 1, false);
             if (rem > 2) row(std::integral_constant<int, 2>{}, y + 2, false);
         } else {
-            // Sliding 5-row window of horizontal sums: ring[s] holds the row
-            // that leaves the window next time slot s is visited.
-            uint32_t ringE[4][4], ringO[4][4];
+            // Sliding 5-row window of horizontal sums in a ring of 5 slots,
+            // one per row of the window: the row entering the window goes to
+            // the slot of the row that left it one output row earlier, so no
+            // slot's old and new values are live at once and the loop carries
+            // every slot in place.  Rows are numbered from y0 - 2: slots 0-3
+            // start with rows y0 - 2 .. y0 + 1; output row y0 + t adds row
+            // t + 4 (slot (t + 4) mod 5) and then drops row t (slot t mod 5).
+            constexpr int R = kBlurRing;
+            uint32_t ringE[R][4], ringO[R][4];
             uint32_t VE[4] = {0, 0, 0, 0}, VO[4] = {0, 0, 0, 0};
 #pragma unroll
             for (int s = 0; s < 4; ++s) {
@@ -409,33 +418,31 @@ static __device__ __forceinline__ void band_tile(const ImgView& V, const OpList&
                     VO[i] += ringO[s][i];
                 }
             }
-            // Input rows y+2 ... are prefetched kPrefetch ahead (kPrefetch
-            // equals the ring length, so every slot index is a constant);
-            // refills are clamped to the last row the tile needs, y1 + 1.
-            // As above, whole groups of four rows loop with no early exit.
+            // Input rows y+2 ... are prefetched R ahead (one slot per row of
+            // an unrolled group, so every slot index is a constant); refills
+            // are clamped to the last row the tile needs, y1 + 1.  As above,
+            // whole groups of R rows loop with no early exit.
             const int last = min(y1 + 1, H - 1);
-            u32x4 nxt[kPrefetch];
+            u32x4 nxt[R];
 #pragma unroll
-            for (int d = 0; d < kPrefetch; ++d) nxt[d] = load_row(min(y0 + 2 + d, last));
+            for (int d = 0; d < R; ++d) nxt[d] = load_row(min(y0 + 2 + d, last));
             auto row = [&](auto kc, int yy, bool refill) {
-                constexpr int k = decltype(kc)::value;
+                constexpr int j = decltype(kc)::value;      // (yy - y0) mod R
+                constexpr int sn = (j + 4) % R;             // slot of the entering row
                 const int rr = min(yy + 2, H - 1);
                 Px4 p;
-                unpack(nxt[k], p);                                                // slot consumed ...
-                if (refill) nxt[k] = load_row(min(yy + 2 + kPrefetch, last));     // ... and refilled
+                unpack(nxt[j], p);                                                // slot consumed ...
+                if (refill) nxt[j] = load_row(min(yy + 2 + R, last));             // ... and refilled
                 apply_ops<PRE>(pre, p, xc, rr, W);
-                uint32_t hE[4], hO[4];
-                hsum5(p.e, hE);
-                hsum5(p.o, hO);
+                hsum5(p.e, ringE[sn]);
+                hsum5(p.o, ringO[sn]);
                 Px4 q;
 #pragma unroll
                 for (int i = 0; i < 4; ++i) {
-                    const uint32_t fe = VE[i] + hE[i];
-                    const uint32_t fo = VO[i] + hO[i];
-                    VE[i] = fe - ringE[k][i];
-                    VO[i] = fo - ringO[k][i];
-                    ringE[k][i] = hE[i];
-                    ringO[k][i] = hO[i];
+                    const uint32_t fe = VE[i] + ringE[sn][i];
+                    const uint32_t fo = VO[i] + ringO[sn][i];
+                    VE[i] = fe - ringE[j][i];
+                    VO[i] = fo - ringO[j][i];
                     q.e[i] = div25_pair(fe);
                     q.o[i] = div25_pair(fo);
                 }
@@ -443,16 +450,18 @@ static __device__ __forceinline__ void band_tile(const ImgView& V, const OpList&
                 emit(q, yy);
             };
             int y = y0;
-            for (; y + 4 <= y1; y += 4) {
+            for (; y + R <= y1; y += R) {
                 row(std::integral_constant<int, 0>{}, y, true);
                 row(std::integral_constant<int, 1>{}, y + 1, true);
                 row(std::integral_constant<int, 2>{}, y + 2, true);
                 row(std::integral_constant<int, 3>{}, y + 3, true);
+                row(std::integral_constant<int, 4>{}, y + 4, true);
             }
             const int rem = y1 - y;
             if (rem > 0) row(std::integral_constant<int, 0>{}, y, false);
             if (rem > 1) row(std::integral_constant<int, 1>{}, y + 1, false);
             if (rem > 2) row(std::integral_constant<int, 2>{}, y + 2, false);
+            if (rem > 3) row(std::integral_constant<int, 3>{}, y + 3, false);
         }
     };
     if (interior)
