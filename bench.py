@@ -561,6 +561,73 @@ def profile_run(steps):
                       "copy_bytes_per_launch": 2 * 8192 * 8192 * 4}), flush=True)
 
 
+def counters_run(steps):
+    """Short run for the counter passes over the other workloads' kernels:
+    a plain copy of an 8192^2 image (the byte-count reference), the
+    256-request batch at its default plan, the FFT -> IFFT chain over 512
+    transforms (passes A, B+A, B), one saxpy stage over 5 x 10^7 elements, one
+    Segmentation stage over 240 x 512 x 512 voxels (`steps` runs each) and
+    one 20-step N-body loop over 65536 bodies."""
+    import torch
+    import paper_1510_06585_amd as sk
+    import synth
+    img = synth.image(synth.SEED_PIPE_FUSED, 8192, 8192)
+    args = image_args(img)
+    copy = sk.Plan(sk.Loop(sk.Map("mirror"), 2), args[:2])   # two mirrors = identity: one copy kernel
+    for _ in range(steps):
+        copy.run(args[:2])
+    torch.cuda.synchronize()
+    copy.destroy()
+    del args
+    sides = synth.batch_sides(synth.SEED_BATCH, 256)
+    reqs = [image_args(synth.image(4000 + r, s, s)) for r, s in enumerate(sides)]
+    proto = [sk.proto([8, 8, 4], sk.U8)] * 2 + [sk.proto([4, 256], sk.U32), sk.proto([4], sk.U64)]
+    bp = sk.Plan(sk.image_chain(PIPE_NSBM, "hist_sum"), proto)
+    bound = sk.bind_batch(reqs)
+    for _ in range(steps):
+        bp.batch_run(bound)
+    torch.cuda.synchronize()
+    bp.destroy()
+    del reqs, bound
+    x = torch.from_numpy(synth.complex_batch(synth.SEED_FFT, 512)).cuda()
+    y = torch.empty_like(x)
+    fp = sk.Plan(sk.image_chain([("fft", {}), ("ifft", {})]), [x, y])
+    for _ in range(steps):
+        fp.run([x, y])
+    torch.cuda.synchronize()
+    fp.destroy()
+    del x, y
+    n = 50_000_000
+    v = torch.from_numpy(synth.vector(11, n)).cuda()
+    w = torch.from_numpy(synth.vector(12, n)).cuda()
+    o = torch.empty_like(v)
+    sp = sk.Plan(sk.Map("saxpy", a=1.5), [v, w, o])
+    for _ in range(steps):
+        sp.run([v, w, o])
+    torch.cuda.synchronize()
+    sp.destroy()
+    del v, w, o
+    vol = torch.from_numpy(synth.gray_volume(synth.SEED_SEGMENT, 240, 512, 512)).cuda()
+    vout = torch.empty_like(vol)
+    gp = sk.Plan(sk.image_chain([("segment", {"lo": 0, "hi": 0})]), [vol, vout])
+    for _ in range(steps):
+        gp.run([vol, vout])
+    torch.cuda.synchronize()
+    gp.destroy()
+    del vol, vout
+    N = 65536
+    pos, vel = synth.nbody(synth.SEED_NBODY, N)
+    nargs = [torch.from_numpy(pos).cuda(), torch.from_numpy(vel).cuda(), torch.empty(N, 4, device="cuda")]
+    npl = sk.Plan(sk.nbody_loop(20), nargs)
+    npl.run(nargs)
+    torch.cuda.synchronize()
+    npl.destroy()
+    torch.cuda.empty_cache()
+    print(json.dumps({"counters_run": {"steps": steps, "batch_requests": 256, "fft_transforms": 512,
+                                       "saxpy_elements": n, "segment_voxels": 240 * 512 * 512,
+                                       "nbody_bodies": N, "nbody_steps": 20}}), flush=True)
+
+
 def mlp_profile_run(n=16384, reps=3):
     """Workload of the MFMA counter pass: the cost-model MLP's forward and
     gradient kernels `reps` times each on n seeded random samples."""
@@ -594,6 +661,8 @@ def main():
     ap.add_argument("--profile-run", action="store_true", help="short run for rocprofv3 counter passes")
     ap.add_argument("--filter-pipeline-only", action="store_true",
                     help="only the 1024x1024 filter pipeline, plain and fused (for a per-stage kernel trace)")
+    ap.add_argument("--counters-run", action="store_true",
+                    help="short run of the other workloads' kernels for rocprofv3 counter passes")
     ap.add_argument("--mlp-profile-run", action="store_true",
                     help="only the cost-model MLP forward and gradient kernels on 16384 samples (MFMA counters)")
     ap.add_argument("--while-only", action="store_true",
@@ -622,6 +691,9 @@ def main():
         return
     if a.mlp_profile_run:
         mlp_profile_run()
+        return
+    if a.counters_run:
+        counters_run(a.steps)
         return
     if a.filter_pipeline_only:
         print(json.dumps(bench_filter_pipeline_1024()), flush=True)

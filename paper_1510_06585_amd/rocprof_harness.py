@@ -81,6 +81,13 @@ def _find(d, key):
     raise KeyError(key)
 
 
+def _find_opt(d, key):
+    for k, v in d.items():
+        if key in k:
+            return v
+    return None
+
+
 def traffic(fetch_csv, write_csv):
     """HBM bytes per launch of the fused kernel, scaled by the copy kernel."""
     f, w = counters(fetch_csv), counters(write_csv)
@@ -250,6 +257,88 @@ def driver_summary(stats_csv, dispatch_csv, bench_json):
     return out
 
 
+COMMANDS_OTHER = (
+    "rocprofv3 --pmc FETCH_SIZE -d DIR -o ofetch --output-format csv -- python3 bench.py --counters-run --steps 5",
+    "rocprofv3 --pmc WRITE_SIZE -d DIR -o owrite --output-format csv -- python3 bench.py --counters-run --steps 5",
+    "rocprofv3 --pmc SQ_WAVES SQ_INSTS_VALU SQ_INSTS_SALU SQ_INSTS_LDS SQ_LDS_BANK_CONFLICT SQ_ACTIVE_INST_VALU "
+    "SQ_BUSY_CYCLES SQ_WAVE_CYCLES -d DIR -o osq --output-format csv -- python3 bench.py --counters-run --steps 3",
+    "python -m paper_1510_06585_amd.rocprof_harness --other-fetch DIR/ofetch_counter_collection.csv "
+    "--other-write DIR/owrite_counter_collection.csv --other-sq DIR/osq_counter_collection.csv --out profiles/",
+)
+SIMDS = 256 * 4          # 4 SIMDs per CU
+SQ_ENGINES = 32          # shader engines summed by SQ_BUSY_CYCLES
+
+
+def other_work():
+    """(kernel-name key, workload, algorithmic bytes per launch, work units per
+    launch, unit name) of the kernels `bench.py --counters-run` launches."""
+    import synth
+    sides = synth.batch_sides(synth.SEED_BATCH, 256)
+    n_fft = 512 * 65536
+    N = 65536
+    return [
+        ("img_batch_kernel<9, 0, true, true, 2>", "256 uneven requests, noise>solarise>blur>mirror + histogram",
+         sum(2 * s * s * 4 + 4128 for s in sides), sum(s * s for s in sides), "pixel"),
+        ("fft_pass_kernel<0>", "FFT pass A, 512 x 65536 complex fp32", 2 * n_fft * 8, n_fft, "element"),
+        ("fft_pass_kernel<1>", "FFT fused pass B+A", 2 * n_fft * 8, n_fft, "element"),
+        ("fft_pass_kernel<2>", "FFT pass B", 2 * n_fft * 8, n_fft, "element"),
+        ("vec_chain_kernel", "saxpy, 5 x 10^7 fp32 (read v, w; write out)", 12 * 50_000_000, 50_000_000,
+         "element"),
+        ("gray_chain_kernel", "Segmentation, 240 x 512 x 512 u8", 2 * 240 * 512 * 512, 240 * 512 * 512, "voxel"),
+        ("nbody_force_kernel<true>", "N-body force + kick-drift, 65536 bodies (one step)",
+         4 * N * 16, N * N, "pair"),
+    ]
+
+
+def other_summary(fetch_csv, write_csv, sq_csv):
+    """Counter summary of the other workloads' kernels: bytes moved between L2
+    and the memory fabric (FETCH_SIZE / WRITE_SIZE scaled by the copy kernel),
+    and VALU instructions per work unit with their share of the busy cycles."""
+    f, w = counters(fetch_csv), counters(write_csv)
+    sq = counters(sq_csv) if sq_csv else {}
+    cf, cw = _find(f, COPY)["FETCH_SIZE"], _find(w, COPY)["WRITE_SIZE"]
+    sf = (COPY_BYTES / 2) / (cf * 1024.0)
+    sw = (COPY_BYTES / 2) / (cw * 1024.0)
+    out = ["# rocprofv3 counters: the kernels of the batched, FFT, saxpy, Segmentation and N-body workloads", "",
+           "Commands (repository root on the MI355X host, TMPDIR=/tmp):", "", "```"] + list(COMMANDS_OTHER) + [
+           "```", "",
+           "`bench.py --counters-run` runs a plain copy of an 8192^2 RGBA image (the byte reference), the "
+           "256-request batch at its default plan, the FFT -> IFFT chain over 512 transforms, one saxpy stage, "
+           "one Segmentation stage (5 runs each in the byte passes, 3 in the SQ pass) and one 20-step N-body "
+           "loop.  FETCH_SIZE and WRITE_SIZE (KiB per dispatch) count what leaves and enters the L2; both are "
+           f"scaled by the copy kernel's known 256 MiB each way (fetch x {sf:.4f}, write x {sw:.4f}).  Where "
+           "the input fits the 256 MB MALL (Segmentation's 60 MiB), fetched bytes may be served there rather "
+           "than by HBM.", "",
+           "## Bytes per launch", "",
+           "| kernel | workload | algorithmic B | fetched B | written B | measured / algorithmic |",
+           "|---|---|---|---|---|---|"]
+    for key, what, algo, units, unit in other_work():
+        fk, wk = _find_opt(f, key), _find_opt(w, key)
+        if not fk or not wk:
+            continue
+        fb = fk["FETCH_SIZE"] * 1024.0 * sf
+        wb = wk["WRITE_SIZE"] * 1024.0 * sw
+        out.append(f"| `{key}` | {what} | {algo} | {fb:.0f} | {wb:.0f} | {(fb + wb) / algo:.3f} |")
+    if sq:
+        out += ["", "## VALU work (SQ counters, mean per dispatch)", "",
+                "VALU lane-instructions per unit = SQ_INSTS_VALU x 64 / units.  Issue share = "
+                f"(SQ_INSTS_VALU x 4 cycles / {SIMDS} SIMDs) / (SQ_BUSY_CYCLES / {SQ_ENGINES} engines): the "
+                "fraction of the busy cycles in which each SIMD issues a VALU instruction.", "",
+                "| kernel | units | SQ_WAVES | SQ_INSTS_VALU | VALU per unit | SQ_INSTS_SALU | SQ_INSTS_LDS | "
+                "SQ_LDS_BANK_CONFLICT | SQ_BUSY_CYCLES | issue share |", "|---|---|---|---|---|---|---|---|---|---|"]
+        for key, what, algo, units, unit in other_work() + [(COPY, "copy", 0, 8192 * 8192, "pixel")]:
+            c = _find_opt(sq, key)
+            if not c:
+                continue
+            valu = c.get("SQ_INSTS_VALU", 0.0)
+            busy = c.get("SQ_BUSY_CYCLES", 0.0)
+            share = (valu * 4.0 / SIMDS) / (busy / SQ_ENGINES) if busy else float("nan")
+            out.append(f"| `{key}` | {units} {unit}s | {c.get('SQ_WAVES', 0):.0f} | {valu:.0f} | "
+                       f"{valu * 64 / units:.2f} | {c.get('SQ_INSTS_SALU', 0):.0f} | {c.get('SQ_INSTS_LDS', 0):.0f} | "
+                       f"{c.get('SQ_LDS_BANK_CONFLICT', 0):.0f} | {busy:.0f} | {share:.3f} |")
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--driver-stats", help="kernel stats of the default bench command under the profiler")
@@ -266,6 +355,9 @@ def main():
     ap.add_argument("--trace-while", help="kernel stats of the 8192x8192 x 10 while Loop run alone")
     ap.add_argument("--while-json", help="the JSON line the traced while run printed (per-iteration wall times)")
     ap.add_argument("--while-dispatches", help="the per-dispatch kernel trace of the same while run")
+    ap.add_argument("--other-fetch", help="FETCH_SIZE pass over bench.py --counters-run")
+    ap.add_argument("--other-write", help="WRITE_SIZE pass over bench.py --counters-run")
+    ap.add_argument("--other-sq", help="SQ counter pass over bench.py --counters-run")
     ap.add_argument("--out", required=True)
     a = ap.parse_args()
     os.makedirs(a.out, exist_ok=True)
@@ -320,6 +412,9 @@ def main():
                    + f", host-checked body {w['host_condition_ms_per_iteration']}, unchecked body "
                    f"{w['no_condition_ms_per_iteration']}."]
         open(os.path.join(a.out, "while_loop_8192.md"), "w").write("\n".join(cw) + "\n")
+    if a.other_fetch and a.other_write:
+        oc = other_summary(a.other_fetch, a.other_write, a.other_sq)
+        open(os.path.join(a.out, "other_kernels_counters.md"), "w").write("\n".join(oc) + "\n")
     if a.mlp_counters:
         cm = counters(a.mlp_counters)
         n = 16384

@@ -86,3 +86,31 @@ def test_last_dispatches_mean(tmp_path):
     _write(p, ["Kind", "Kernel_Name", "Start_Timestamp", "End_Timestamp"], rows)
     assert rh.last_dispatches(str(p), "img_batch_kernel", 3) == 20.0
     assert rh.last_dispatches(str(p), "img_batch_kernel", 6) is None
+
+
+def test_other_summary_scales_bytes_by_the_copy_kernel(tmp_path):
+    """Bytes are the counter readings times (known copy bytes / the copy
+    kernel's reading), per direction; VALU per unit and the issue share
+    follow from the SQ readings."""
+    copy = "void skel::img_band_kernel<0, 0, false, false, 0>(skel::ImgGroupArgs)"
+    seg = "skel::gray_chain_kernel(skel::GrayArgs)"
+    half = rh.COPY_BYTES // 2
+    vox = 240 * 512 * 512
+    hdr = ["Kernel_Name", "Counter_Name", "Counter_Value"]
+    # the copy reads back half its bytes in FETCH_SIZE and all of them in
+    # WRITE_SIZE: scales 2 and 1; the Segmentation kernel reads 30 and 20 MiB
+    _write(tmp_path / "f.csv", hdr, [[copy, "FETCH_SIZE", str(half / 2048)], [copy, "FETCH_SIZE", str(half / 2048)],
+                                     [seg, "FETCH_SIZE", str(30 * 1024)]])
+    _write(tmp_path / "w.csv", hdr, [[copy, "WRITE_SIZE", str(half / 1024)], [seg, "WRITE_SIZE", str(20 * 1024)]])
+    busy = 32 * 1000.0
+    valu = 1024 * 500 / 4.0          # each SIMD issues for 500 of its 1000 busy cycles
+    _write(tmp_path / "s.csv", hdr, [[seg, "SQ_INSTS_VALU", str(valu)], [seg, "SQ_BUSY_CYCLES", str(busy)],
+                                     [seg, "SQ_WAVES", "4096"]])
+    out = "\n".join(rh.other_summary(str(tmp_path / "f.csv"), str(tmp_path / "w.csv"), str(tmp_path / "s.csv")))
+    mib = 1 << 20
+    algo = 2 * vox
+    assert (f"| `gray_chain_kernel` | Segmentation, 240 x 512 x 512 u8 | {algo} | {60 * mib} | {20 * mib} | "
+            f"{80 * mib / algo:.3f} |") in out
+    assert f"| {valu:.0f} | {valu * 64 / vox:.2f} |" in out
+    assert out.rstrip().endswith("| 0.500 |")
+    assert "fetch x 2.0000, write x 1.0000" in out
