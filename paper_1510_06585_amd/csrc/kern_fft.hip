@@ -51,9 +51,10 @@ static __device__ __forceinline__ cpx cmul_i(cpx a) { return DIR < 0 ? cpx{a.y, 
 
 // Roots of unity in LDS: TH[h] = W^(256 h) and TL[l] = W^l (h, l < 256,
 // W = exp(2 pi i / N)), so W^m = TH[m >> 8] TL[m & 255] from two reads
-// instead of a scattered read of a 512 KiB table.
+// instead of a scattered read of a 512 KiB table; T16[l] = W^(16 l) (l < 16)
+// for the stride-16 products of the transposed stores.
 struct TwLds {
-    cpx hi[256], lo[256];
+    cpx hi[256], lo[256], s16[16];
 };
 
 static __device__ __forceinline__ void load_tw(TwLds& L, const float2* T) {
@@ -61,6 +62,10 @@ static __device__ __forceinline__ void load_tw(TwLds& L, const float2* T) {
         const float2 h = T[256 * i], l = T[i];
         L.hi[i] = {h.x, h.y};
         L.lo[i] = {l.x, l.y};
+        if (i < 16) {
+            const float2 q = T[16 * i];
+            L.s16[i] = {q.x, q.y};
+        }
     }
 }
 
@@ -169,13 +174,28 @@ static __device__ __forceinline__ void dft256_reg(cpx* S, const TwLds& T, const 
 }
 
 // Twiddle W_N^(n1 k2) (n1 = kFftCols g + j, k2 = m) and store T[k2][n1].
+// A thread stores one column j = t mod kFftCols at the rows m = m0 + 16 i
+// (m0 = t / kFftCols, i < 16), so its twiddles are W^(n1 m0) W^(16 k) with
+// k = n1 i mod 4096, and W^(16 k) = TH[k >> 4] T16[k & 15].  Across a
+// wavefront these two indices are nearly consecutive or shared, so the
+// reads avoid LDS bank conflicts; only W^(n1 m0) is a scattered lookup, once
+// per thread.
 template <int DIR>
 static __device__ __forceinline__ void store_twiddled(const cpx* S, const TwLds& W, cpx* out, int g) {
+    static_assert(kFftThreads % kFftCols == 0 && kFftThreads / kFftCols == 16, "one column, rows m0 + 16 i");
     const int t = threadIdx.x;
+    const int j = t % kFftCols, m0 = t / kFftCols;
+    const uint32_t n1 = (uint32_t)(kFftCols * g + j);
+    const cpx a = tw<DIR>(W, n1 * (uint32_t)m0);
 #pragma unroll
     for (int i = 0; i < 16; ++i) {
-        const int e = t + kFftThreads * i, j = e % kFftCols, m = e / kFftCols;
-        const cpx w = tw<DIR>(W, (uint32_t)(kFftCols * g + j) * (uint32_t)m);
+        const int m = m0 + 16 * i;
+        cpx w = a;
+        if (i > 0) {
+            const uint32_t k = (n1 * (uint32_t)i) & 4095u;
+            const cpx c = cmul(W.hi[k >> 4], W.s16[k & 15u]);
+            w = cmul(a, cpx{c.x, DIR < 0 ? -c.y : c.y});
+        }
         out[m * kFftR + kFftCols * g + j] = cmul(S[sx(j, m)], w);
     }
 }
