@@ -420,7 +420,11 @@ skel_status skel_time_config(skel_node root, const skel_buffer* args, int32_t na
  * the features describe a square image of the batch's total pixel count.
  * Writes the fastest options to *best (fusion ON, tile_h, wg), its median to
  * *best_us and the number of points timed to *timed (both may be NULL).
- * Synchronises the device; the requests' outputs are overwritten. */
+ * Before any device work the request set gets skel_batch_run's host-side
+ * checks, so a bad request returns that call's status and message (EINVAL,
+ * ESHAPE, EUNSUPPORTED); a candidate that fails to run afterwards is
+ * SKEL_EDEVICE.  Synchronises the device; the requests' outputs are
+ * overwritten. */
 skel_status skel_tune_batch(skel_node root, const skel_buffer* args, int32_t nargs, int32_t nreq,
                             const char* db_path, int32_t reps, int32_t pruned, double precision_us,
                             skel_plan_opts* best, double* best_us, int32_t* timed);

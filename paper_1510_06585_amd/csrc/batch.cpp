@@ -116,9 +116,10 @@ skel_status check_disjoint(const skel_buffer* args, int nargs, int nreq, int red
 
 }  // namespace
 
-extern "C" skel_status skel_batch_run(skel_plan p, const skel_buffer* args, int32_t nargs, int32_t nreq,
-                                      void* stream) {
-    clear_error();
+namespace {
+
+// The plan and every request on their own (no device work).
+skel_status check_requests(skel_plan p, const skel_buffer* args, int32_t nargs, int32_t nreq) {
     if (!p) return set_error(SKEL_EINVAL, "null plan");
     if (p->lin.dom != DOM_U8 || p->kernels.size() != 1)
         return set_error(SKEL_EUNSUPPORTED, "batched runs need a fully fused image plan (one kernel)");
@@ -126,13 +127,29 @@ extern "C" skel_status skel_batch_run(skel_plan p, const skel_buffer* args, int3
     if (nreq < 0 || (nreq > 0 && !args)) return set_error(SKEL_EINVAL, "bad request array");
     if (nreq > 65535) return set_error(SKEL_EUNSUPPORTED, "at most 65535 requests per batch");
     const Kernel& K = p->kernels[0];
-    const int red = p->lin.red;
     const bool inplace_ok = !(K.blur || K.img.in_flip || K.img.out_flip);
     for (int r = 0; r < nreq; ++r) {
-        skel_status st = check_req(args + (size_t)r * nargs, nargs, red, r, inplace_ok);
+        skel_status st = check_req(args + (size_t)r * nargs, nargs, p->lin.red, r, inplace_ok);
         if (st) return st;
     }
+    return SKEL_OK;
+}
+
+}  // namespace
+
+skel_status batch_validate(skel_plan p, const skel_buffer* args, int32_t nargs, int32_t nreq) {
+    skel_status st = check_requests(p, args, nargs, nreq);
+    if (st || nreq == 0) return st;
+    return check_disjoint(args, nargs, nreq, p->lin.red);
+}
+
+extern "C" skel_status skel_batch_run(skel_plan p, const skel_buffer* args, int32_t nargs, int32_t nreq,
+                                      void* stream) {
+    clear_error();
+    if (skel_status st = check_requests(p, args, nargs, nreq)) return st;
     if (nreq == 0) return SKEL_OK;
+    const Kernel& K = p->kernels[0];
+    const int red = p->lin.red;
     const hipStream_t s = (hipStream_t)stream;
     // Rows per tile: the plan's tile_h when it was given, else kBatchTileRows
     // for every request.  With work-groups taking groups of adjacent tiles,

@@ -178,6 +178,11 @@ skel_status noalloc_prepare(skel_plan p, const skel_buffer* args, int32_t nargs,
 // Enqueues the plan's kernels with its scratch in `region` (device memory of
 // at least L.total bytes); the plan's own scratch pointers are left as they were.
 skel_status noalloc_run(skel_plan p, const skel_buffer* args, void* stream, char* region, const NoallocLayout& L);
+
+// The host-side checks skel_batch_run makes of a request set (the plan, every
+// request on its own, then the requests' buffers against each other), with no
+// device work.
+skel_status batch_validate(skel_plan p, const skel_buffer* args, int32_t nargs, int32_t nreq);
 // Resolves the device address of the static scratch array on `device` (which
 // must be current) once; later calls are no-ops.
 skel_status noalloc_setup(int device);

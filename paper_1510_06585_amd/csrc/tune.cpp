@@ -593,6 +593,19 @@ extern "C" skel_status skel_tune_batch(skel_node root, const skel_buffer* args, 
     if (!st) st = derive_shape(L, args, nargs, sh);
     if (st) return st;
     if (L.dom != DOM_U8 || L.is_while) return set_error(SKEL_EUNSUPPORTED, "batched runs are image chains");
+    {
+        // The request set is checked on the host before any device work, so a
+        // bad request reports its own status rather than a failed candidate's.
+        skel_plan_opts o;
+        skel_plan_opts_default(&o);
+        o.fusion = SKEL_FUSE_ON;
+        skel_plan p0 = nullptr;
+        if ((st = skel_plan_compile(root, args, nargs, &o, &p0))) return st;
+        st = batch_validate(p0, args, nargs, nreq);
+        const std::string why = st ? skel_last_error() : "";
+        skel_plan_destroy(p0);   // clears the thread's error message
+        if (st) return set_error(st, "%s", why.c_str());
+    }
     if (reps <= 0) reps = 10;
     if (precision_us < 0) precision_us = 0;
     // The knowledge-base row describes the whole batch: the key names the

@@ -247,6 +247,28 @@ def _img_req(base, H, W):
             _dense([4, 256], sk.U32, base + 2 * n), _dense([4], sk.U64, base + 2 * n + 4096)]
 
 
+def test_tune_batch_checks_the_request_set_on_the_host():
+    """The batch autotuner checks the request set before any device work, so a
+    bad request reports its own status (here on a machine with no GPU)."""
+    root = sk.image_chain(PIPE_NSBM, "hist_sum")
+    H, W = 8, 8
+    a = _img_req(1 << 40, H, W)
+    a[1].data = a[0].data + 16                       # in and out overlap partially
+    with pytest.raises(sk.SkelError) as e:
+        sk.tune_batch(root, [a])
+    assert e.value.status == sk.EINVAL and "overlap" in str(e.value)
+    a, b = _img_req(1 << 40, H, W), _img_req(1 << 41, H, W)
+    b[2].data = a[2].data                            # two requests share a histogram
+    with pytest.raises(sk.SkelError) as e:
+        sk.tune_batch(root, [a, b])
+    assert e.value.status == sk.EINVAL
+    a, b = _img_req(1 << 40, H, W), _img_req(1 << 41, H, W)
+    b[2] = _dense([4, 128], sk.U32, b[2].data)       # wrong histogram shape
+    with pytest.raises(sk.SkelError) as e:
+        sk.tune_batch(root, [a, b])
+    assert e.value.status == sk.ESHAPE
+
+
 def test_mixed_zero_strides_are_rejected():
     # strides may be all zero (dense shorthand) or exactly dense; a zero stride
     # next to non-zero ones would make the kernels read past the allocation
