@@ -22,6 +22,10 @@ corrects for the share of the memory channels the counters observe.
       --fetch DIR/fetch_counter_collection.csv \
       --write DIR/write_counter_collection.csv --sq DIR/sq_counter_collection.csv --out profiles/
 
+``--trace-all`` / ``--trace-all-dispatches`` alone rewrite only the whole-run
+summary (``bench_all_kernels.md``), and ``--other-fetch`` / ``--other-write`` /
+``--other-sq`` the counter summary of the other workloads' kernels.
+
 The while Loop's trace (``bench.py --while-only`` under the trace command in
 COMMAND_WHILE, its stdout kept in a file) is summarised with
 ``--trace-while DIR/while8192_kernel_stats.csv --while-json FILE
@@ -435,6 +439,18 @@ def main():
             if mops:
                 ml.append(f"| `{short}` | MFMA flops (MOPS x 512) | {mops * 512:.0f} |")
         open(os.path.join(a.out, "mlp_mfma_16384.md"), "w").write("\n".join(ml) + "\n")
+    if a.trace_all:
+        al = ["# rocprofv3 kernel trace of the whole bench run (every skeleton's kernels)", "",
+              "Command (repository root on the MI355X host, TMPDIR=/tmp):", "", "```", COMMANDS[1], "```", "",
+              "Averages mix workloads where one kernel serves several (e.g. the fused image kernel runs the "
+              "8192^2 image and, in the sequential baseline of the batch, 256 smaller ones).", "",
+              "| kernel | calls | avg us | min us | max us |", "|---|---|---|---|---|"]
+        stats_all = kernel_stats(a.trace_all)
+        for r in stats_all:
+            al.append(f"| `{r['name'][:90]}` | {r['calls']} | {r['avg_ns']/1e3:.2f} | {r['min_ns']/1e3:.2f} | "
+                      f"{r['max_ns']/1e3:.2f} |")
+        al += row_roofline(stats_all, a.trace_all_dispatches)
+        open(os.path.join(a.out, "bench_all_kernels.md"), "w").write("\n".join(al) + "\n")
     if not (a.trace and a.fetch and a.write):
         return
     st = kernel_stats(a.trace)
@@ -463,18 +479,6 @@ def main():
             for c, v in sorted(_find(sq, kern).items()):
                 lines.append(f"| `{kern}` | {c} | {v:.0f} |")
     open(os.path.join(a.out, f"{FUSED_NAME}_8192.md"), "w").write("\n".join(lines) + "\n")
-    if a.trace_all:
-        al = ["# rocprofv3 kernel trace of the whole bench run (every skeleton's kernels)", "",
-              "Command (repository root on the MI355X host, TMPDIR=/tmp):", "", "```", COMMANDS[1], "```", "",
-              "Averages mix workloads where one kernel serves several (e.g. the fused image kernel runs the "
-              "8192^2 image and, in the sequential baseline of the batch, 256 smaller ones).", "",
-              "| kernel | calls | avg us | min us | max us |", "|---|---|---|---|---|"]
-        stats_all = kernel_stats(a.trace_all)
-        for r in stats_all:
-            al.append(f"| `{r['name'][:90]}` | {r['calls']} | {r['avg_ns']/1e3:.2f} | {r['min_ns']/1e3:.2f} | "
-                      f"{r['max_ns']/1e3:.2f} |")
-        al += row_roofline(stats_all, a.trace_all_dispatches)
-        open(os.path.join(a.out, "bench_all_kernels.md"), "w").write("\n".join(al) + "\n")
     print(json.dumps(rec))
 
 
