@@ -403,7 +403,9 @@ skel_status ensure_resources(skel_plan p) {
     size_t bytes = 0;
     if (p->lin.dom == DOM_U8) bytes = (size_t)(p->sh.W * p->sh.H * 4);
     if (p->lin.dom == DOM_F32) bytes = (size_t)(p->sh.n * 4);
-    if (p->lin.dom == DOM_C32) bytes = (size_t)p->sh.n * kFftPoints * 8;
+    // transposed intermediates take 256 rows of kFftTRow per transform (natural
+    // order between unfused stages takes less)
+    if (p->lin.dom == DOM_C32) bytes = (size_t)p->sh.n * 256 * kFftTRow * 8;
     if (p->lin.dom == DOM_GRAY) bytes = (size_t)p->sh.n;
     for (int k = 0; k < nscr; ++k)
         if (!p->scratch[k]) HIP_TRY(hipMalloc(&p->scratch[k], std::max<size_t>(bytes, 16)));

@@ -207,6 +207,10 @@ struct FftArgs {
     float scale1;        // applied to a stage's pass-B result (1/65536 after an inverse)
 };
 constexpr int kFftPoints = 65536;
+// Row stride, in complex elements, of the transposed layout T[k2][n1] that
+// passes exchange through plan scratch: 256 + 16 keeps every row on a 128-byte
+// line boundary while breaking the power-of-two stride of the column runs.
+constexpr int kFftTRow = 256 + 16;
 hipError_t launch_fft_pass(const FftArgs& a, int mode, hipStream_t s);
 const char* fft_pass_name(int mode);
 

@@ -196,7 +196,7 @@ static __device__ __forceinline__ void store_twiddled(const cpx* S, const TwLds&
             const cpx c = cmul(W.hi[k >> 4], W.s16[k & 15u]);
             w = cmul(a, cpx{c.x, DIR < 0 ? -c.y : c.y});
         }
-        out[m * kFftR + kFftCols * g + j] = cmul(S[sx(j, m)], w);
+        out[m * kFftTRow + kFftCols * g + j] = cmul(S[sx(j, m)], w);
     }
 }
 
@@ -212,8 +212,11 @@ __global__ void __launch_bounds__(kFftThreads) fft_pass_kernel(const FftArgs A) 
     const int b = blockIdx.x / (kFftR / kFftCols);
     const int g = blockIdx.x % (kFftR / kFftCols);
     const int t = threadIdx.x;
-    const cpx* in = reinterpret_cast<const cpx*>(A.in) + (size_t)b * kFftN;
-    cpx* out = reinterpret_cast<cpx*>(A.out) + (size_t)b * kFftN;
+    // natural order: kFftN elements per transform; transposed (a pass A
+    // output, a pass B input): 256 rows of kFftTRow
+    constexpr size_t kT = (size_t)kFftR * kFftTRow;
+    const cpx* in = reinterpret_cast<const cpx*>(A.in) + (size_t)b * (MODE == 0 ? (size_t)kFftN : kT);
+    cpx* out = reinterpret_cast<cpx*>(A.out) + (size_t)b * (MODE == 2 ? (size_t)kFftN : kT);
     const int j = t >> 4, u = t & 15;
     cpx v[16];   // v[c] = element u + 16 c of row j of the tile
     if (MODE == 0) {
@@ -228,10 +231,10 @@ __global__ void __launch_bounds__(kFftThreads) fft_pass_kernel(const FftArgs A) 
 #pragma unroll
         for (int c = 0; c < 16; ++c) v[c] = S[sx(j, u + 16 * c)];
     } else {
-        // row k2 = kFftCols g + j of T (T[k2][m] at k2 * 256 + m), straight
-        // into registers: for each c the 16 threads of a row read one
+        // row k2 = kFftCols g + j of T (T[k2][m] at k2 * kFftTRow + m),
+        // straight into registers: for each c the 16 threads of a row read one
         // 128-byte run
-        const cpx* row = in + (size_t)(kFftCols * g + j) * kFftR;
+        const cpx* row = in + (size_t)(kFftCols * g + j) * kFftTRow;
 #pragma unroll
         for (int c = 0; c < 16; ++c) v[c] = row[u + 16 * c];
         __syncthreads();   // the twiddle tables
