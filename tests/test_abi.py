@@ -269,6 +269,19 @@ def test_tune_batch_checks_the_request_set_on_the_host():
     assert e.value.status == sk.ESHAPE
 
 
+def test_tune_batch_rejects_empty_and_non_image_request_sets():
+    root = sk.image_chain(PIPE_NSBM, "hist_sum")
+    with pytest.raises(sk.SkelError) as e:       # no requests at all
+        sk.tune_batch(root, [])
+    assert e.value.status == sk.EINVAL
+    n = 1000                                      # an fp32 chain is not a batched image run
+    vec = [_dense([n], sk.F32, 1 << 40), _dense([n], sk.F32, (1 << 40) + 4 * n),
+           _dense([n], sk.F32, (1 << 40) + 8 * n)]
+    with pytest.raises(sk.SkelError) as e:
+        sk.tune_batch(sk.Map("saxpy", a=1.0), [vec])
+    assert e.value.status == sk.EUNSUPPORTED
+
+
 def test_mixed_zero_strides_are_rejected():
     # strides may be all zero (dense shorthand) or exactly dense; a zero stride
     # next to non-zero ones would make the kernels read past the allocation
